@@ -1,0 +1,154 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) adaptive point-charge Laplace FMM.
+ *
+ * The library evaluates, for N point charges q_j at positions r_j,
+ *
+ *     u(r_i)   = -1/(4 pi) * sum_{j : |r_i - r_j| > 0} q_j / |r_i - r_j|
+ *     E(r_i)   = -grad u(r_i)
+ *
+ * (kernel and density of eqs. 2-3 of Kraft et al., "jaxFMM: An Adaptive,
+ * GPU-Parallel Implementation of the Fast Multipole Method in JAX",
+ * arXiv 2511.15269), approximately, by the paper's fast multipole method:
+ * a balanced 2^s-tree built by median splits (Sec. II.A), cross-level
+ * interaction lists from the admissibility test R + theta r <= theta d
+ * (eq. 4, Sec. II.B), real solid-harmonic expansions of order p
+ * (Sec. II.C, App. A) and rotation-based O(p^3) M2M/M2L/L2L operators
+ * computed per interaction (Sec. II.D, App. B).  Pairs at distance 0
+ * contribute nothing.  Every pass runs as hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" must be device memory of the current
+ *     HIP device; "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream); all
+ *     device work is enqueued on it.  fmm_plan_create and the fmm_plan_get_*
+ *     calls synchronise that stream; fmm_evaluate does not.
+ *   - Every call returns an fmm_status.  On any error no output buffer has
+ *     been written, the plan (if any) is unchanged and usable, and
+ *     fmm_last_error() returns a message for the calling thread.
+ *   - No C++ exception crosses this boundary.
+ */
+#ifndef FMM_H_
+#define FMM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_ABI_VERSION 1
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_EINVAL = 1,  /* bad argument: parameter out of range, NULL pointer,
+                      non-finite position, size mismatch                  */
+  FMM_ENOMEM = 2,  /* device allocation failed                             */
+  FMM_EDEVICE = 3, /* HIP runtime error (launch, copy, wrong device)       */
+  FMM_ENOTSUP = 4, /* valid request this build does not implement
+                      (e.g. an expansion order without compiled kernels)   */
+  FMM_ESTATE = 5   /* plan in a state that does not allow the call         */
+} fmm_status;
+
+typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
+
+typedef enum { FMM_TIE_SOURCE = 0, FMM_TIE_TARGET = 1 } fmm_tie;
+
+/* Method parameters (Sec. II.A-II.B; Table II). */
+typedef struct {
+  int p;            /* expansion order, 1 <= p <= FMM_MAX_ORDER            */
+  int leaf_max;     /* N_max: levels are added until every box holds at
+                       most leaf_max points; must be >= 2^splits            */
+  int splits;       /* s: binary splits per level, 1..3 (2^s children)   */
+  double theta;     /* separation parameter of eq. 4, 0 < theta < 1        */
+  int max_depth;    /* cap on the number of levels L, 0..16                */
+  int precision;    /* fmm_precision of charges, expansions and outputs    */
+  int tie_refine;   /* fmm_tie: side refined when the level-mean radii of
+                       source and target level are equal (Sec. II.B, the
+                       enumerated rule 2 says source)                      */
+  int max_rhs;      /* largest number of charge vectors per evaluate, >= 1 */
+} fmm_params;
+
+#define FMM_MAX_ORDER 10
+
+typedef struct fmm_plan fmm_plan;
+
+/* Sizes of a built plan. */
+typedef struct {
+  int64_t n;            /* points                                          */
+  int32_t depth;        /* L (leaf level)                                  */
+  int32_t splits;       /* s                                               */
+  int64_t nbox;         /* boxes over all levels, sum_l 2^{s l}            */
+  int64_t nleaf;        /* 2^{s L}                                         */
+  int64_t n_m2l;        /* multipole-to-local pairs (all levels)           */
+  int64_t n_p2p;        /* leaf-leaf direct pairs (including self pairs)   */
+  int64_t p2p_interactions; /* sum over direct pairs of |src| * |tgt|     */
+  int64_t device_bytes; /* device memory held by the plan                  */
+} fmm_plan_info;
+
+/* Version of this ABI (FMM_ABI_VERSION of the built library). */
+int fmm_abi_version(void);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* fmm_last_error(void);
+
+/* Build the tree, box geometry and interaction lists of `n` points.
+ *   pos    device, double[n][3] (x, y, z of point i at pos[3i..3i+2]), read
+ *          only; the plan keeps its own copy, so the caller may free or
+ *          overwrite pos after the call returns.
+ *   n      1 <= n < 2^31.
+ *   prm    host, parameters (copied).
+ *   out    host, receives the new plan (owned by the caller; free it with
+ *          fmm_plan_destroy).  Untouched on error.
+ * Tree: Sec. II.A (median split along the longest axis; the lower child
+ * takes ceil(n/2) points ordered by (coordinate, input index); the first
+ * axis wins ties of the extent).  Geometry: centre = midpoint of the tight
+ * bounding box of a box's points, radius = half its diagonal.  Lists: the
+ * cross-level level march of Sec. II.B; a pair at distance 0 is never
+ * admissible.  Errors: FMM_EINVAL (parameters, n, NULL, non-finite
+ * position), FMM_ENOTSUP (p above FMM_MAX_ORDER), FMM_ENOMEM, FMM_EDEVICE. */
+fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
+                           void* stream, fmm_plan** out);
+
+/* Sizes of the plan (host struct, written on success). */
+fmm_status fmm_plan_get_info(const fmm_plan* plan, fmm_plan_info* info);
+
+/* Evaluate potentials (and fields) for `nrhs` charge vectors.
+ *   q      device, [nrhs][n] of double (FMM_FP64) or float (FMM_FP32),
+ *          in input point order.
+ *   pot    device, [nrhs][n], same type: u at every input point.
+ *   field  device, [nrhs][n][3], same type: -grad u; may be NULL (then
+ *          only potentials are computed).
+ * 1 <= nrhs <= max_rhs of the plan.  Enqueued on `stream`; buffers must
+ * stay valid until the stream has executed it.  Calls on one plan must be
+ * serialised by the caller (they share the plan's expansion workspace).
+ * Errors: FMM_EINVAL (NULL q or pot, nrhs out of range), FMM_EDEVICE. */
+fmm_status fmm_evaluate(fmm_plan* plan, const void* q, int nrhs, void* pot,
+                        void* field, void* stream);
+
+/* Copy the tree to host buffers (any may be NULL):
+ *   perm       int64[n]: leaf-ordered slot i holds input point perm[i]
+ *   leaf_start int64[nleaf+1]: leaf j holds slots [leaf_start[j],
+ *              leaf_start[j+1]); points inside a leaf by input index
+ *   centre     double[nbox][3], radius double[nbox]; box b of level l has
+ *              global id (2^{s l} - 1)/(2^s - 1) + b, children of b are
+ *              b * 2^s + c. */
+fmm_status fmm_plan_get_tree(const fmm_plan* plan, int64_t* perm,
+                             int64_t* leaf_start, double* centre,
+                             double* radius);
+
+/* Copy the interaction lists to host buffers (any may be NULL), each
+ * sorted by (target, source):
+ *   m2l_src/m2l_tgt  int64[n_m2l], global box ids
+ *   p2p_src/p2p_tgt  int64[n_p2p], leaf indices */
+fmm_status fmm_plan_get_lists(const fmm_plan* plan, int64_t* m2l_src,
+                              int64_t* m2l_tgt, int64_t* p2p_src,
+                              int64_t* p2p_tgt);
+
+/* Release the plan and its device memory (NULL is accepted). */
+fmm_status fmm_plan_destroy(fmm_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H_ */

@@ -33,21 +33,26 @@ from .tree import Tree, build_tree
 
 
 def multipoles(tree: Tree, pos: np.ndarray, q: np.ndarray, p: int,
-               chunk: int = 1 << 15) -> np.ndarray:
-    """C[B, (p+1)^2]: direct P2M of every box about its own centre."""
+               boxes: np.ndarray | None = None, chunk: int = 1 << 15) -> np.ndarray:
+    """C[B, (p+1)^2]: direct P2M of every box (or of the global ids in
+    ``boxes``; the others stay zero) about its own centre."""
     K = ncoef(p)
     C = np.zeros((tree.nbox, K))
     pl = pos[tree.perm]
     ql = q[tree.perm]
-    n = len(pl)
     leaf_of = np.repeat(np.arange(tree.nleaf), np.diff(tree.leaf_start))
+    want = None
+    if boxes is not None:
+        want = np.zeros(tree.nbox, dtype=bool)
+        want[np.asarray(boxes, dtype=np.int64)] = True
     for l in range(tree.L + 1):
         box = tree.level_off[l] + (leaf_of >> (tree.s * (tree.L - l)))
-        for c0 in range(0, n, chunk):
-            c1 = min(n, c0 + chunk)
-            b = box[c0:c1]
-            d = pl[c0:c1] - tree.centre[b]
-            Rq = ql[c0:c1, None] * regular(p, d[:, 0], d[:, 1], d[:, 2])
+        sel = np.arange(len(pl)) if want is None else np.flatnonzero(want[box])
+        for c0 in range(0, len(sel), chunk):
+            ix = sel[c0:c0 + chunk]
+            b = box[ix]
+            d = pl[ix] - tree.centre[b]
+            Rq = ql[ix, None] * regular(p, d[:, 0], d[:, 1], d[:, 2])
             cut = np.flatnonzero(np.diff(b)) + 1
             starts = np.concatenate([[0], cut])
             C[b[starts]] += np.add.reduceat(Rq, starts, axis=0)
@@ -101,7 +106,8 @@ def fmm(pos: np.ndarray, q: np.ndarray, p: int, leaf_max: int, s: int = 2,
     tleaf = np.searchsorted(tree.leaf_start, tslot, side="right") - 1
     anc = _ancestors(tree, tleaf)
     need = np.unique(anc)
-    C = multipoles(tree, pos, q, p)
+    srcs = np.unique(lists.m2l_src[np.isin(lists.m2l_tgt, need)])
+    C = multipoles(tree, pos, q, p, boxes=srcs)
     D = locals_from_m2l(tree, lists, C, p, targets_boxes=need)
     x = pos[targets]
     u = np.zeros(len(targets))

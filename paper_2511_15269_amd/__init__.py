@@ -1,0 +1,122 @@
+"""MI355X-native adaptive point-charge Laplace FMM (Kraft et al., jaxFMM,
+arXiv 2511.15269), Python binding of the C ABI in ``include/fmm.h``.
+
+PyTorch supplies device memory and the stream; the tree, lists and every
+evaluation stage run inside ``libfmm.so`` (hand-written HIP kernels for
+gfx950).  There is no fallback: without the built library or a GPU the
+calls raise.
+
+    plan = Plan(pos, p=8, leaf_max=128, splits=2, theta=0.7)
+    pot, field = plan.evaluate(q)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import (FMM_FP32, FMM_FP64, FMM_TIE_SOURCE, FMM_TIE_TARGET, FMMError,
+                   FmmParams, FmmPlanInfo, check, lib)
+
+__all__ = ["Plan", "FMMError", "params"]
+
+
+def params(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16,
+           precision="fp64", tie="source", max_rhs=1) -> FmmParams:
+    return FmmParams(p=p, leaf_max=leaf_max, splits=splits, theta=float(theta),
+                     max_depth=max_depth,
+                     precision=FMM_FP64 if precision == "fp64" else FMM_FP32,
+                     tie_refine=FMM_TIE_SOURCE if tie == "source" else FMM_TIE_TARGET,
+                     max_rhs=max_rhs)
+
+
+def _stream_ptr(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Tree, geometry and interaction lists of a fixed point set (the
+    paper's cached hierarchy), reusable for any number of charge vectors."""
+
+    def __init__(self, pos: torch.Tensor, p=8, leaf_max=128, splits=2, theta=0.7,
+                 max_depth=16, precision="fp64", tie="source", max_rhs=1, stream=None):
+        if not (isinstance(pos, torch.Tensor) and pos.is_cuda):
+            raise ValueError("pos must be a CUDA tensor")
+        if pos.dim() != 2 or pos.shape[1] != 3:
+            raise ValueError("pos must have shape [N, 3]")
+        pos = pos.to(torch.float64).contiguous()
+        self.n = pos.shape[0]
+        self.device = pos.device
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.max_rhs = max_rhs
+        self._prm = params(p, leaf_max, splits, theta, max_depth, precision, tie, max_rhs)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_create(ctypes.c_void_p(pos.data_ptr()), self.n,
+                                        ctypes.byref(self._prm), _stream_ptr(stream),
+                                        ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().fmm_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def info(self) -> dict:
+        inf = FmmPlanInfo()
+        check(lib().fmm_plan_get_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in FmmPlanInfo._fields_}
+
+    def evaluate(self, q: torch.Tensor, field: bool = True, out=None, stream=None):
+        """Potentials (and fields = -grad u) for charges ``q`` ([N] or
+        [R, N], CUDA, plan precision).  Returns (pot, field or None)."""
+        if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == self.dtype):
+            raise ValueError(f"q must be a CUDA {self.dtype} tensor")
+        single = q.dim() == 1
+        qq = q.reshape(1, -1) if single else q
+        if qq.shape[1] != self.n:
+            raise ValueError("q has the wrong number of points")
+        qq = qq.contiguous()
+        R = qq.shape[0]
+        if out is None:
+            pot = torch.empty((R, self.n), dtype=self.dtype, device=q.device)
+            fld = torch.empty((R, self.n, 3), dtype=self.dtype, device=q.device) if field else None
+        else:
+            pot, fld = out
+        with torch.cuda.device(self.device):
+            check(lib().fmm_evaluate(self._h, ctypes.c_void_p(qq.data_ptr()), R,
+                                     ctypes.c_void_p(pot.data_ptr()),
+                                     ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
+                                     _stream_ptr(stream)))
+        if single:
+            return pot[0], (fld[0] if fld is not None else None)
+        return pot, fld
+
+    def tree(self):
+        """(perm, leaf_start, centre[B,3], radius[B]) as numpy arrays."""
+        inf = self.info()
+        perm = np.empty(inf["n"], np.int64)
+        ls = np.empty(inf["nleaf"] + 1, np.int64)
+        c = np.empty((inf["nbox"], 3), np.float64)
+        r = np.empty(inf["nbox"], np.float64)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        PD = ctypes.POINTER(ctypes.c_double)
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_get_tree(self._h, perm.ctypes.data_as(P64), ls.ctypes.data_as(P64),
+                                          c.ctypes.data_as(PD), r.ctypes.data_as(PD)))
+        return perm, ls, c, r
+
+    def lists(self):
+        """(m2l_src, m2l_tgt, p2p_src, p2p_tgt), sorted by (target, source)."""
+        inf = self.info()
+        a = [np.empty(inf["n_m2l"], np.int64), np.empty(inf["n_m2l"], np.int64),
+             np.empty(inf["n_p2p"], np.int64), np.empty(inf["n_p2p"], np.int64)]
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_get_lists(self._h, *[x.ctypes.data_as(P64) for x in a]))
+        return tuple(a)

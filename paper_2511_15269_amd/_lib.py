@@ -1,0 +1,67 @@
+"""ctypes declarations of the C ABI in ``include/fmm.h`` (argument
+marshalling only; every computation happens in ``libfmm.so``)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ENOTSUP, FMM_ESTATE = range(6)
+STATUS_NAMES = {0: "FMM_OK", 1: "FMM_EINVAL", 2: "FMM_ENOMEM", 3: "FMM_EDEVICE",
+                4: "FMM_ENOTSUP", 5: "FMM_ESTATE"}
+FMM_FP64, FMM_FP32 = 0, 1
+FMM_TIE_SOURCE, FMM_TIE_TARGET = 0, 1
+
+
+class FmmParams(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("leaf_max", ctypes.c_int),
+                ("splits", ctypes.c_int), ("theta", ctypes.c_double),
+                ("max_depth", ctypes.c_int), ("precision", ctypes.c_int),
+                ("tie_refine", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+
+
+class FmmPlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("splits", ctypes.c_int32), ("nbox", ctypes.c_int64),
+                ("nleaf", ctypes.c_int64), ("n_m2l", ctypes.c_int64),
+                ("n_p2p", ctypes.c_int64), ("p2p_interactions", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "python -m paper_2511_15269_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i64p, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        L.fmm_abi_version.restype = ctypes.c_int
+        L.fmm_last_error.restype = ctypes.c_char_p
+        L.fmm_plan_create.argtypes = [vp, i64, ctypes.POINTER(FmmParams), vp, ctypes.POINTER(vp)]
+        L.fmm_plan_get_info.argtypes = [vp, ctypes.POINTER(FmmPlanInfo)]
+        L.fmm_evaluate.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+        L.fmm_plan_get_tree.argtypes = [vp, i64p, i64p, dp, dp]
+        L.fmm_plan_get_lists.argtypes = [vp, i64p, i64p, i64p, i64p]
+        L.fmm_plan_destroy.argtypes = [vp]
+        for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
+                  "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != FMM_OK:
+        raise FMMError(status, lib().fmm_last_error().decode())

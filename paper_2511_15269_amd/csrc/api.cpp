@@ -1,0 +1,255 @@
+// C ABI of the FMM library: argument checks, plan lifetime, error strings.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "internal.h"
+#include "tables.h"
+
+namespace fmm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+void* plan_alloc(fmm_plan* pl, size_t bytes) {
+  void* p = nullptr;
+  bytes = bytes ? bytes : 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{FMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  pl->bufs.push_back(DevBuf{p, bytes});
+  pl->device_bytes += bytes;
+  return p;
+}
+
+void plan_free_all(fmm_plan* pl) {
+  for (auto& b : pl->bufs) (void)hipFree(b.ptr);
+  pl->bufs.clear();
+  pl->device_bytes = 0;
+}
+
+namespace {
+
+int depth_for(int64_t n, int leaf, int s, int max_depth) {
+  int L = 0;
+  while (L < max_depth) {
+    const int64_t per = (n + ((int64_t)1 << (L * s)) - 1) >> (L * s);  // ceil
+    if (per <= leaf) break;
+    ++L;
+  }
+  return L;
+}
+
+void check_params(const fmm_params* prm, int64_t n) {
+  if (!prm) throw Error{FMM_EINVAL, "params is NULL"};
+  if (n < 1 || n >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "n must be in [1, 2^31)"};
+  if (prm->splits < 1 || prm->splits > 3) throw Error{FMM_EINVAL, "splits must be 1..3"};
+  if (prm->p < 1) throw Error{FMM_EINVAL, "p must be >= 1"};
+  if (prm->leaf_max < (1 << prm->splits))
+    throw Error{FMM_EINVAL, "leaf_max must be >= 2^splits"};
+  if (!(prm->theta > 0.0 && prm->theta < 1.0)) throw Error{FMM_EINVAL, "theta must be in (0,1)"};
+  if (prm->max_depth < 0 || prm->max_depth > 16) throw Error{FMM_EINVAL, "max_depth must be 0..16"};
+  if (prm->precision != FMM_FP64 && prm->precision != FMM_FP32)
+    throw Error{FMM_EINVAL, "precision must be FMM_FP64 or FMM_FP32"};
+  if (prm->tie_refine != FMM_TIE_SOURCE && prm->tie_refine != FMM_TIE_TARGET)
+    throw Error{FMM_EINVAL, "tie_refine must be FMM_TIE_SOURCE or FMM_TIE_TARGET"};
+  if (prm->max_rhs < 1) throw Error{FMM_EINVAL, "max_rhs must be >= 1"};
+  if (prm->p > FMM_MAX_ORDER) throw Error{FMM_ENOTSUP, "p above FMM_MAX_ORDER"};
+}
+
+template <typename F>
+fmm_status guard(F&& f) {
+  try {
+    clear_error();
+    f();
+    return FMM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FMM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return FMM_EDEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return FMM_EDEVICE;
+  }
+}
+
+void check_device(const fmm_plan* pl) {
+  int dev = -1;
+  FMM_HIP(hipGetDevice(&dev));
+  if (dev != pl->device)
+    throw Error{FMM_EDEVICE, "current device differs from the plan's device"};
+}
+
+}  // namespace
+}  // namespace fmm
+
+using namespace fmm;
+
+extern "C" {
+
+int fmm_abi_version(void) { return FMM_ABI_VERSION; }
+
+const char* fmm_last_error(void) { return fmm::last_error(); }
+
+fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
+                           void* stream, fmm_plan** out) {
+  return guard([&] {
+    if (!out) throw Error{FMM_EINVAL, "out is NULL"};
+    if (!pos) throw Error{FMM_EINVAL, "pos is NULL"};
+    check_params(prm, n);
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<fmm_plan> pl(new fmm_plan());
+    try {
+      FMM_HIP(hipGetDevice(&pl->device));
+      pl->prm = *prm;
+      pl->n = n;
+      pl->s = prm->splits;
+      pl->nch = 1 << pl->s;
+      pl->L = depth_for(n, prm->leaf_max, pl->s, prm->max_depth);
+      pl->level_off.assign(pl->L + 2, 0);
+      for (int l = 0; l <= pl->L; ++l)
+        pl->level_off[l + 1] = pl->level_off[l] + ((int64_t)1 << (pl->s * l));
+      pl->nbox = pl->level_off[pl->L + 1];
+      pl->nleaf = (int64_t)1 << (pl->s * pl->L);
+      if (pl->nbox >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "too many boxes"};
+      pl->perm = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * n);
+      pl->leaf_start = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * (pl->nleaf + 1));
+      pl->xs = (double*)plan_alloc(pl.get(), sizeof(double) * n);
+      pl->ys = (double*)plan_alloc(pl.get(), sizeof(double) * n);
+      pl->zs = (double*)plan_alloc(pl.get(), sizeof(double) * n);
+      pl->cx = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      pl->cy = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      pl->cz = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      pl->radius = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      build_tree(pl.get(), pos, st);
+      build_lists(pl.get(), st);
+      const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+      const size_t K = (size_t)ncoef(prm->p);
+      pl->q_leaf = plan_alloc(pl.get(), es * (size_t)n);
+      pl->C = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
+      pl->D = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
+      pl->partial = plan_alloc(pl.get(), es * K * (size_t)std::max<int64_t>(pl->n_items, 1));
+      pl->tables = get_tables(prm->p, prm->precision, pl->device);
+      FMM_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      plan_free_all(pl.get());
+      throw;
+    }
+    *out = pl.release();
+  });
+}
+
+fmm_status fmm_plan_get_info(const fmm_plan* pl, fmm_plan_info* info) {
+  return guard([&] {
+    if (!pl || !info) throw Error{FMM_EINVAL, "NULL argument"};
+    fmm_plan_info r{};
+    r.n = pl->n;
+    r.depth = pl->L;
+    r.splits = pl->s;
+    r.nbox = pl->nbox;
+    r.nleaf = pl->nleaf;
+    r.n_m2l = pl->n_m2l;
+    r.n_p2p = pl->n_p2p;
+    r.p2p_interactions = pl->p2p_inter;
+    r.device_bytes = (int64_t)pl->device_bytes;
+    *info = r;
+  });
+}
+
+fmm_status fmm_evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot,
+                        void* field, void* stream) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
+    if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
+    check_device(pl);
+    fmm::evaluate(pl, q, nrhs, pot, field, (hipStream_t)stream);
+  });
+}
+
+fmm_status fmm_plan_get_tree(const fmm_plan* pl, int64_t* perm, int64_t* leaf_start,
+                             double* centre, double* radius) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    check_device(pl);
+    std::vector<int32_t> p32;
+    if (perm) {
+      p32.resize(pl->n);
+      FMM_HIP(hipMemcpy(p32.data(), pl->perm, sizeof(int32_t) * pl->n, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> l32;
+    if (leaf_start) {
+      l32.resize(pl->nleaf + 1);
+      FMM_HIP(hipMemcpy(l32.data(), pl->leaf_start, sizeof(int32_t) * (pl->nleaf + 1),
+                        hipMemcpyDeviceToHost));
+    }
+    std::vector<double> c[3], r;
+    if (centre) {
+      const double* src[3] = {pl->cx, pl->cy, pl->cz};
+      for (int a = 0; a < 3; ++a) {
+        c[a].resize(pl->nbox);
+        FMM_HIP(hipMemcpy(c[a].data(), src[a], sizeof(double) * pl->nbox, hipMemcpyDeviceToHost));
+      }
+    }
+    if (radius) {
+      r.resize(pl->nbox);
+      FMM_HIP(hipMemcpy(r.data(), pl->radius, sizeof(double) * pl->nbox, hipMemcpyDeviceToHost));
+    }
+    for (size_t i = 0; i < p32.size(); ++i) perm[i] = p32[i];
+    for (size_t i = 0; i < l32.size(); ++i) leaf_start[i] = l32[i];
+    if (centre)
+      for (int64_t b = 0; b < pl->nbox; ++b)
+        for (int a = 0; a < 3; ++a) centre[3 * b + a] = c[a][b];
+    if (radius) std::memcpy(radius, r.data(), sizeof(double) * pl->nbox);
+  });
+}
+
+fmm_status fmm_plan_get_lists(const fmm_plan* pl, int64_t* m2l_src, int64_t* m2l_tgt,
+                              int64_t* p2p_src, int64_t* p2p_tgt) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    check_device(pl);
+    auto fetch = [&](const int32_t* ptr_d, const int32_t* src_d, int64_t ntgt, int64_t nk,
+                     int64_t* src, int64_t* tgt) {
+      if (!src && !tgt) return;
+      std::vector<int32_t> ptr(ntgt + 1), s(std::max<int64_t>(nk, 1));
+      FMM_HIP(hipMemcpy(ptr.data(), ptr_d, sizeof(int32_t) * (ntgt + 1), hipMemcpyDeviceToHost));
+      if (nk > 0)
+        FMM_HIP(hipMemcpy(s.data(), src_d, sizeof(int32_t) * nk, hipMemcpyDeviceToHost));
+      for (int64_t t = 0; t < ntgt; ++t)
+        for (int32_t k = ptr[t]; k < ptr[t + 1]; ++k) {
+          if (src) src[k] = s[k];
+          if (tgt) tgt[k] = t;
+        }
+    };
+    fetch(pl->m2l_ptr, pl->m2l_src, pl->nbox, pl->n_m2l, m2l_src, m2l_tgt);
+    fetch(pl->p2p_ptr, pl->p2p_src, pl->nleaf, pl->n_p2p, p2p_src, p2p_tgt);
+  });
+}
+
+fmm_status fmm_plan_destroy(fmm_plan* pl) {
+  return guard([&] {
+    if (!pl) return;
+    (void)hipSetDevice(pl->device);
+    (void)hipDeviceSynchronize();
+    plan_free_all(pl);
+    delete pl;
+  });
+}
+
+}  // extern "C"

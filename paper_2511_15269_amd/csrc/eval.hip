@@ -1,0 +1,613 @@
+// FMM evaluation pass (stage order of Sec. III.A: sort, P2M, M2M, M2L, L2L,
+// L2P, P2P), hand-written HIP kernels for gfx950.
+//
+// Coefficients are kept normalised (tables.h), box-major: [box][(P+1)^2].
+// All translations are rotation based (Sec. II.D, App. B): for a shift from
+// an old centre to a new one with b = old - new = r (sin B cos A,
+// sin B sin A, cos B), the coefficients are rotated so that b points along
+// +z, shifted with the diagonal z-axis operators of App. B.3 and rotated
+// back.  The rotation about y by B is factored as
+//   Rz(-pi/2) Ry(-pi/2) Rz(B) Ry(pi/2) Rz(pi/2)
+// so each interaction needs four products with the fixed per-degree block
+// Y_n (or its transpose) and azimuthal 2x2 rotations (App. B.1) by angles
+// built from A and B; the Rz(+-pi/2) next to the z-axis operator cancel
+// because that operator commutes with rotations about z.  One thread owns
+// one interaction (all of its coefficients sit in registers); the operator
+// tables are wave-uniform and are read through the scalar cache.
+//
+//   M2L item: thread = (target box, up to 16 of its sources); partial sums
+//             are added per target in a fixed order by the L2L kernel, so
+//             results do not depend on scheduling (no atomics).
+//   M2M:      thread = child box; the 2^s children of a parent sit in
+//             adjacent lanes and are summed with cross-lane shuffles.
+//   L2L:      thread = box of the level; adds its M2L partials and the
+//             shifted local expansion of its parent.
+//   P2M:      block = leaf, thread = point, LDS reduction over points.
+//   L2P+P2P:  block = target leaf, thread = target point; the source
+//             leaves of the direct list are read with wave-uniform loads.
+#include <cmath>
+
+#include "internal.h"
+#include "tables.h"
+
+namespace fmm {
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+constexpr int kM2LThreads = 64;
+
+template <int P>
+struct K_ {
+  static constexpr int value = (P + 1) * (P + 1);
+};
+
+// cos(m g), sin(m g), m = 0..P, by repeated complex multiplication
+template <int P, typename T>
+__device__ __forceinline__ void powers(T c1, T s1, T* c, T* s) {
+  c[0] = T(1);
+  s[0] = T(0);
+#pragma unroll
+  for (int m = 1; m <= P; ++m) {
+    c[m] = c[m - 1] * c1 - s[m - 1] * s1;
+    s[m] = s[m - 1] * c1 + c[m - 1] * s1;
+  }
+}
+
+// (v^m, v^{-m}) <- (a c + b s, b c - a s) for every degree, with
+// (c, s) = (cm[m], sgn * sm[m]) after the quarter-turn shift q (m*q*pi/2
+// added to the angle; q in {0, 1}): q = 1 maps (cos ma, sin ma) to
+// (cos m(pi/2 - a), sin m(pi/2 - a)).
+template <int P, typename T, int SGN, int Q>
+__device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
+#pragma unroll
+  for (int m = 1; m <= P; ++m) {
+    T c, s;
+    if (Q == 0) {
+      c = cm[m];
+      s = sm[m];
+    } else {
+      switch (m & 3) {
+        case 0: c = cm[m]; s = -sm[m]; break;
+        case 1: c = sm[m]; s = cm[m]; break;
+        case 2: c = -cm[m]; s = sm[m]; break;
+        default: c = -sm[m]; s = -cm[m]; break;
+      }
+    }
+    if (SGN < 0) s = -s;
+#pragma unroll
+    for (int n = m; n <= P; ++n) {
+      T a = v[cidx(n, m)], b = v[cidx(n, -m)];
+      v[cidx(n, m)] = a * c + b * s;
+      v[cidx(n, -m)] = b * c - a * s;
+    }
+  }
+}
+
+// v_n <- Y_n v_n (TR: Y_n^T v_n); zero entries are skipped at compile time
+template <int P, bool TR, typename T>
+__device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
+#pragma unroll
+  for (int n = 1; n <= P; ++n) {
+    const T* Y = tab + tab_y(P) + ybase(n);
+    const int w = 2 * n + 1;
+    T u[2 * P + 1];
+#pragma unroll
+    for (int a = -n; a <= n; ++a) {
+      T acc = T(0);
+#pragma unroll
+      for (int b = -n; b <= n; ++b) {
+        if ((a >= 0) != (b >= 0)) continue;
+        const int par = ((a < 0 ? -a : a) + (b < 0 ? -b : b) + n) & 1;
+        if ((a >= 0 && par) || (a < 0 && !par)) continue;
+        const T y = TR ? Y[(b + n) * w + (a + n)] : Y[(a + n) * w + (b + n)];
+        acc = fma(y, v[cidx(n, b)], acc);
+      }
+      u[a + n] = acc;
+    }
+#pragma unroll
+    for (int a = -n; a <= n; ++a) v[cidx(n, a)] = u[a + n];
+  }
+}
+
+enum { kM2M = 0, kM2L = 1, kL2L = 2 };
+
+// z-axis operators of App. B.3 (normalised), in place
+template <int P, int KIND, typename T>
+__device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
+  if (KIND == kM2L) {
+    const T ir = T(1) / r;
+    T ip[2 * P + 2];
+    ip[0] = T(1);
+#pragma unroll
+    for (int j = 1; j <= 2 * P + 1; ++j) ip[j] = ip[j - 1] * ir;
+#pragma unroll
+    for (int n = 0; n <= P; ++n)
+#pragma unroll
+      for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= ip[n];
+#pragma unroll
+    for (int m = -P; m <= P; ++m) {
+      const int am = m < 0 ? -m : m;
+      T o[P + 1];
+#pragma unroll
+      for (int n = am; n <= P; ++n) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = am; k <= P; ++k)
+          acc = fma(tab[tab_tm2l(P) + t3(P, n, k, am)], v[cidx(k, m)], acc);
+        o[n] = acc * ip[n + 1];
+      }
+#pragma unroll
+      for (int n = am; n <= P; ++n) v[cidx(n, m)] = m < 0 ? -o[n] : o[n];
+    }
+  } else {
+    T pw[P + 1];
+    pw[0] = T(1);
+#pragma unroll
+    for (int j = 1; j <= P; ++j) pw[j] = pw[j - 1] * r;
+#pragma unroll
+    for (int m = -P; m <= P; ++m) {
+      const int am = m < 0 ? -m : m;
+      T o[P + 1];
+#pragma unroll
+      for (int n = am; n <= P; ++n) {
+        T acc = T(0);
+        if (KIND == kM2M) {
+#pragma unroll
+          for (int k = am; k <= n; ++k)
+            acc = fma(tab[tab_tm2m(P) + t3(P, n, k, am)] * pw[n - k], v[cidx(k, m)], acc);
+        } else {
+#pragma unroll
+          for (int k = n; k <= P; ++k)
+            acc = fma(tab[tab_tl2l(P) + t3(P, n, k, am)] * pw[k - n], v[cidx(k, m)], acc);
+        }
+        o[n] = acc;
+      }
+#pragma unroll
+      for (int n = am; n <= P; ++n) v[cidx(n, m)] = o[n];
+    }
+  }
+}
+
+// Rotate so that b points along +z, shift along z, rotate back.
+// b = old centre - new centre.  M2L maps multipole (regular-basis sign
+// convention) to local (singular-basis convention); M2M keeps the former,
+// L2L the latter.
+template <int P, int KIND, typename T>
+__device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double bz,
+                                             const T* __restrict__ tab) {
+  const double rxy2 = bx * bx + by * by;
+  const double rxy = sqrt(rxy2);
+  const double r = sqrt(rxy2 + bz * bz);
+  double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
+  if (rxy > 0.0) {
+    ca = bx / rxy;
+    sa = by / rxy;
+  }
+  if (r > 0.0) {
+    cb = bz / r;
+    sb = rxy / r;
+  }
+  T am_c[P + 1], am_s[P + 1], bm_c[P + 1], bm_s[P + 1];
+  powers<P, T>(T(ca), T(sa), am_c, am_s);
+  powers<P, T>(T(cb), T(sb), bm_c, bm_s);
+  // forward: Rz(pi/2 - A), Y, Rz(-B), Y^T   (sign conventions per kind)
+  if (KIND == kL2L)
+    azimuth<P, T, -1, 1>(v, am_c, am_s);
+  else
+    azimuth<P, T, +1, 1>(v, am_c, am_s);
+  apply_y<P, false, T>(v, tab);
+  if (KIND == kL2L)
+    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
+  else
+    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
+  apply_y<P, true, T>(v, tab);
+  zshift<P, KIND, T>(v, T(r), tab);
+  // back: Y, Rz(B), Y^T, Rz(A - pi/2)
+  apply_y<P, false, T>(v, tab);
+  if (KIND == kM2M)
+    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
+  else
+    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
+  apply_y<P, true, T>(v, tab);
+  if (KIND == kM2M)
+    azimuth<P, T, -1, 1>(v, am_c, am_s);
+  else
+    azimuth<P, T, +1, 1>(v, am_c, am_s);
+}
+
+// ---------------------------------------------------------------- P2M
+// Regular basis R-hat^m_n(x, y, z) in degree-major order by the App. A.1
+// recursions; calls f(k, value) for k = 0..K-1 as values become available.
+template <int P, typename T, typename F>
+__device__ __forceinline__ void regular_basis(T x, T y, T z, F&& f) {
+  const T r2 = x * x + y * y + z * z;
+  T sc = T(1), ss = T(0);  // sectoral R^{m}_{m}, R^{-m}_{m}
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (m == 1) {
+      sc = x * T(0.5);
+      ss = -y * T(0.5);
+    } else if (m >= 2) {
+      const T nc = (x * sc + y * ss) * T(1.0 / (2 * m));
+      const T ns = (x * ss - y * sc) * T(1.0 / (2 * m));
+      sc = nc;
+      ss = ns;
+    }
+    f(cidx(m, m), sc);
+    if (m > 0) f(cidx(m, -m), ss);
+    T p2c = T(0), p2s = T(0), p1c = sc, p1s = ss;
+#pragma unroll
+    for (int n = m + 1; n <= P; ++n) {
+      T c, s;
+      if (n == m + 1) {
+        c = z * p1c;
+        s = z * p1s;
+      } else {
+        const T inv = T(1.0 / ((n - m) * (n + m)));
+        c = (T(2 * n - 1) * z * p1c - r2 * p2c) * inv;
+        s = (T(2 * n - 1) * z * p1s - r2 * p2s) * inv;
+      }
+      f(cidx(n, m), c);
+      if (m > 0) f(cidx(n, -m), s);
+      p2c = p1c;
+      p2s = p1s;
+      p1c = c;
+      p1s = s;
+    }
+  }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(64) void k_p2m(
+    int nleaf, int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const double* __restrict__ xs, const double* __restrict__ ys,
+    const double* __restrict__ zs, const T* __restrict__ q,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const T* __restrict__ tab, T* __restrict__ C) {
+  constexpr int K = K_<P>::value;
+  __shared__ T red[K][65];
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t g = leaf_box0 + leaf;
+  const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  const double ox = cx[g], oy = cy[g], oz = cz[g];
+  for (int j = st + lane; j < en; j += 64) {
+    const T qj = q[j];
+    regular_basis<P, T>(T(xs[j] - ox), T(ys[j] - oy), T(zs[j] - oz),
+                        [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k][lane] = acc[k];
+  __syncthreads();
+  for (int k = lane; k < K; k += 64) {
+    T s = T(0);
+    for (int l = 0; l < 64; ++l) s += red[k][l];
+    C[g * K + k] = s * tab[tab_normc(P) + k];
+  }
+}
+
+// ---------------------------------------------------------------- M2M
+template <int P, typename T>
+__global__ __launch_bounds__(64) void k_m2m(
+    int64_t nchild, int64_t child0, int64_t parent0, int s,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const T* __restrict__ tab, T* C) {
+  constexpr int K = K_<P>::value;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < nchild;
+  const int64_t c = child0 + (live ? i : 0);
+  const int64_t pa = parent0 + ((live ? i : 0) >> s);
+  T v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = live ? C[c * K + k] : T(0);
+  rotate_shift<P, kM2M, T>(v, cx[c] - cx[pa], cy[c] - cy[pa], cz[c] - cz[pa], tab);
+  const int nch = 1 << s;
+  for (int off = 1; off < nch; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  if (live && (i & (nch - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) C[pa * K + k] = v[k];
+  }
+}
+
+// ---------------------------------------------------------------- M2L
+template <int P, typename T>
+__global__ __launch_bounds__(kM2LThreads) void k_m2l(
+    int64_t nitems, const int32_t* __restrict__ item_tgt,
+    const int32_t* __restrict__ item_begin, const int32_t* __restrict__ item_end,
+    const int32_t* __restrict__ src, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const T* __restrict__ C, const T* __restrict__ tab, T* __restrict__ partial) {
+  constexpr int K = K_<P>::value;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nitems) return;
+  const int t = item_tgt[i];
+  const int jb = item_begin[i], je = item_end[i];
+  const double tx = cx[t], ty = cy[t], tz = cz[t];
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  for (int j = jb; j < je; ++j) {
+    const int sidx = src[j];
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = C[(int64_t)sidx * K + k];
+    rotate_shift<P, kM2L, T>(v, cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, tab);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) partial[i * K + k] = acc[k];
+}
+
+// ---------------------------------------------------------------- L2L
+// D_t = (M2L partials of t, in item order) + L2L(D_parent)
+template <int P, typename T>
+__global__ __launch_bounds__(64) void k_l2l(
+    int64_t nb, int64_t box0, int64_t parent0, int s,
+    const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const T* __restrict__ tab, T* D) {
+  constexpr int K = K_<P>::value;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int64_t t = box0 + i;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  for (int it = item_ptr[t]; it < item_ptr[t + 1]; ++it) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += partial[(int64_t)it * K + k];
+  }
+  if (parent0 >= 0) {
+    const int64_t pa = parent0 + (i >> s);
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
+    rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], tab);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v[k];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) D[t * K + k] = acc[k];
+}
+
+// ---------------------------------------------------------------- L2P+P2P
+// Regular basis and its gradient (App. A.1, A.3; the sectoral gradient
+// without the printed leading minus), accumulated against w[k] = weight *
+// local coefficient: pot += w R, grad += w grad R.
+template <int P, typename T>
+__device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ w,
+                                           T& pot, T& gx, T& gy, T& gz) {
+  const T r2 = x * x + y * y + z * z;
+  // sectoral value and gradient (z component of a sectoral gradient is 0)
+  T sc = T(1), ss = T(0), scx = T(0), scy = T(0), ssx = T(0), ssy = T(0);
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (m == 1) {
+      sc = x * T(0.5);
+      ss = -y * T(0.5);
+      scx = T(0.5);
+      scy = T(0);
+      ssx = T(0);
+      ssy = T(-0.5);
+    } else if (m >= 2) {
+      const T f = T(1.0 / (2 * m));
+      const T nc = (x * sc + y * ss) * f;
+      const T ns = (x * ss - y * sc) * f;
+      const T ncx = (x * scx + y * ssx + sc) * f;
+      const T ncy = (x * scy + y * ssy + ss) * f;
+      const T nsx = (x * ssx - y * scx + ss) * f;
+      const T nsy = (x * ssy - y * scy - sc) * f;
+      sc = nc; ss = ns; scx = ncx; scy = ncy; ssx = nsx; ssy = nsy;
+    }
+    {
+      const T wc = w[cidx(m, m)];
+      pot = fma(wc, sc, pot);
+      gx = fma(wc, scx, gx);
+      gy = fma(wc, scy, gy);
+      if (m > 0) {
+        const T ws = w[cidx(m, -m)];
+        pot = fma(ws, ss, pot);
+        gx = fma(ws, ssx, gx);
+        gy = fma(ws, ssy, gy);
+      }
+    }
+    // previous two degrees for +m (c) and -m (s): value, gradient
+    T c2 = T(0), c2x = T(0), c2y = T(0), c2z = T(0);
+    T s2 = T(0), s2x = T(0), s2y = T(0), s2z = T(0);
+    T c1 = sc, c1x = scx, c1y = scy, c1z = T(0);
+    T s1 = ss, s1x = ssx, s1y = ssy, s1z = T(0);
+#pragma unroll
+    for (int n = m + 1; n <= P; ++n) {
+      T c, cxg, cyg, czg, s, sxg, syg, szg;
+      if (n == m + 1) {
+        c = z * c1; cxg = z * c1x; cyg = z * c1y; czg = z * c1z + c1;
+        s = z * s1; sxg = z * s1x; syg = z * s1y; szg = z * s1z + s1;
+      } else {
+        const T inv = T(1.0 / ((n - m) * (n + m)));
+        const T a = T(2 * n - 1);
+        c = (a * z * c1 - r2 * c2) * inv;
+        cxg = (a * (z * c1x) - r2 * c2x - T(2) * c2 * x) * inv;
+        cyg = (a * (z * c1y) - r2 * c2y - T(2) * c2 * y) * inv;
+        czg = (a * (z * c1z + c1) - r2 * c2z - T(2) * c2 * z) * inv;
+        s = (a * z * s1 - r2 * s2) * inv;
+        sxg = (a * (z * s1x) - r2 * s2x - T(2) * s2 * x) * inv;
+        syg = (a * (z * s1y) - r2 * s2y - T(2) * s2 * y) * inv;
+        szg = (a * (z * s1z + s1) - r2 * s2z - T(2) * s2 * z) * inv;
+      }
+      const T wc = w[cidx(n, m)];
+      pot = fma(wc, c, pot);
+      gx = fma(wc, cxg, gx);
+      gy = fma(wc, cyg, gy);
+      gz = fma(wc, czg, gz);
+      if (m > 0) {
+        const T ws = w[cidx(n, -m)];
+        pot = fma(ws, s, pot);
+        gx = fma(ws, sxg, gx);
+        gy = fma(ws, syg, gy);
+        gz = fma(ws, szg, gz);
+      }
+      c2 = c1; c2x = c1x; c2y = c1y; c2z = c1z;
+      s2 = s1; s2x = s1x; s2y = s1y; s2z = s1z;
+      c1 = c; c1x = cxg; c1y = cyg; c1z = czg;
+      s1 = s; s1x = sxg; s1y = syg; s1z = szg;
+    }
+  }
+}
+
+__device__ __forceinline__ double inv_sqrt(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  y = y * (1.5 - 0.5 * r2 * y * y);
+  y = y * (1.5 - 0.5 * r2 * y * y);
+  return y;
+}
+__device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+template <int P, typename T, bool FIELD>
+__global__ __launch_bounds__(64) void k_l2p_p2p(
+    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ perm, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const T* __restrict__ q, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const T* __restrict__ D, const int32_t* __restrict__ p2p_ptr,
+    const int32_t* __restrict__ p2p_src, const T* __restrict__ tab,
+    T* __restrict__ pot, T* __restrict__ field) {
+  constexpr int K = K_<P>::value;
+  __shared__ T w[K];
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t g = leaf_box0 + leaf;
+  for (int k = lane; k < K; k += 64) w[k] = D[g * K + k] * tab[tab_l2p(P) + k];
+  __syncthreads();
+  const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
+  const double ox = cx[g], oy = cy[g], oz = cz[g];
+  const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
+  for (int i = st + lane; i - lane < en; i += 64) {
+    const bool live = i < en;
+    const int ii = live ? i : st;
+    const double xi = xs[ii], yi = ys[ii], zi = zs[ii];
+    T fp = T(0), fx = T(0), fy = T(0), fz = T(0);
+    local_eval<P, T>(T(xi - ox), T(yi - oy), T(zi - oz), w, fp, fx, fy, fz);
+    // near field: sum q/r and q (xi - xj)/r^3 over the direct list
+    T np_ = T(0), nx = T(0), ny = T(0), nz = T(0);
+    for (int k = pb; k < pe; ++k) {
+      const int sl = p2p_src[k];
+      const int js = leaf_start[sl], je = leaf_start[sl + 1];
+      for (int j = js; j < je; ++j) {
+        const T dx = T(xi - xs[j]), dy = T(yi - ys[j]), dz = T(zi - zs[j]);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T inv = r2 > T(0) ? inv_sqrt(r2) : T(0);
+        const T qi = q[j] * inv;
+        np_ += qi;
+        if (FIELD) {
+          const T q3 = qi * inv * inv;
+          nx = fma(q3, dx, nx);
+          ny = fma(q3, dy, ny);
+          nz = fma(q3, dz, nz);
+        }
+      }
+    }
+    if (live) {
+      const int o = perm[i];
+      // u = -1/(4 pi) (far sum + near sum);  field = -grad u
+      pot[o] = -T(kInv4Pi) * (fp + np_);
+      if (FIELD) {
+        field[3 * (int64_t)o + 0] = T(kInv4Pi) * (fx - nx);
+        field[3 * (int64_t)o + 1] = T(kInv4Pi) * (fy - ny);
+        field[3 * (int64_t)o + 2] = T(kInv4Pi) * (fz - nz);
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm,
+                         const T* __restrict__ q, T* __restrict__ ql) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) ql[j] = q[perm[j]];
+}
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int P, typename T>
+void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
+  constexpr int K = K_<P>::value;
+  const int L = pl->L, s = pl->s;
+  const T* tab = (const T*)pl->tables;
+  T* ql = (T*)pl->q_leaf;
+  T* C = (T*)pl->C;
+  T* D = (T*)pl->D;
+  T* part = (T*)pl->partial;
+  const int64_t n = pl->n;
+  const int64_t leaf0 = pl->level_off[L];
+  k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, q, ql);
+  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+      (int)pl->nleaf, leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs, ql, pl->cx,
+      pl->cy, pl->cz, tab, C);
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t nchild = pl->level_off[l + 2] - pl->level_off[l + 1];
+    k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(
+        nchild, pl->level_off[l + 1], pl->level_off[l], s, pl->cx, pl->cy,
+        pl->cz, tab, C);
+  }
+  if (pl->n_items > 0)
+    k_m2l<P, T><<<blocks(pl->n_items, kM2LThreads), kM2LThreads, 0, st>>>(
+        pl->n_items, pl->item_tgt, pl->item_begin, pl->item_end, pl->m2l_src,
+        pl->cx, pl->cy, pl->cz, C, tab, part);
+  for (int l = 0; l <= L; ++l) {
+    const int64_t nb = pl->level_off[l + 1] - pl->level_off[l];
+    k_l2l<P, T><<<blocks(nb, 64), 64, 0, st>>>(
+        nb, pl->level_off[l], l > 0 ? pl->level_off[l - 1] : -1, s,
+        pl->item_ptr, part, pl->cx, pl->cy, pl->cz, tab, D);
+  }
+  if (field)
+    k_l2p_p2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, ql, pl->cx,
+        pl->cy, pl->cz, D, pl->p2p_ptr, pl->p2p_src, tab, pot, field);
+  else
+    k_l2p_p2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, ql, pl->cx,
+        pl->cy, pl->cz, D, pl->p2p_ptr, pl->p2p_src, tab, pot, field);
+  FMM_HIP(hipGetLastError());
+  (void)K;
+}
+
+template <typename T>
+void dispatch(int p, fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
+  switch (p) {
+#define FMM_CASE(PP) \
+  case PP:           \
+    run<PP, T>(pl, q, pot, field, st); \
+    break;
+    FMM_CASE(1) FMM_CASE(2) FMM_CASE(3) FMM_CASE(4) FMM_CASE(5)
+    FMM_CASE(6) FMM_CASE(7) FMM_CASE(8) FMM_CASE(9) FMM_CASE(10)
+#undef FMM_CASE
+    default:
+      throw Error{FMM_ENOTSUP, "expansion order without compiled kernels"};
+  }
+}
+
+}  // namespace
+
+void evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot, void* field,
+              hipStream_t st) {
+  const int64_t n = pl->n;
+  for (int r = 0; r < nrhs; ++r) {
+    if (pl->prm.precision == FMM_FP32) {
+      dispatch<float>(pl->prm.p, pl, (const float*)q + r * n, (float*)pot + r * n,
+                      field ? (float*)field + 3 * r * n : nullptr, st);
+    } else {
+      dispatch<double>(pl->prm.p, pl, (const double*)q + r * n, (double*)pot + r * n,
+                       field ? (double*)field + 3 * r * n : nullptr, st);
+    }
+  }
+}
+
+}  // namespace fmm

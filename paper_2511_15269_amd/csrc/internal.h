@@ -1,0 +1,123 @@
+// Internal declarations of the FMM library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+// Status carried through host code; converted to fmm_status at the ABI.
+struct Error {
+  fmm_status code;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define FMM_HIP(call)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      throw ::fmm::Error{e_ == hipErrorOutOfMemory ? FMM_ENOMEM            \
+                                                   : FMM_EDEVICE,          \
+                         std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device buffer owned by a plan.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Constant operator tables of one expansion order (values in double; the
+// float path keeps a rounded copy).  Layouts are shared with the kernels in
+// eval.hip through the index helpers of tables.h.
+struct Tables {
+  int p = -1;
+  std::vector<double> host;  // all tables, concatenated
+  void* dev64 = nullptr;     // device copy (double)
+  void* dev32 = nullptr;     // device copy (float)
+};
+
+}  // namespace fmm
+
+struct fmm_plan {
+  int device = 0;
+  fmm_params prm{};
+  int64_t n = 0;
+  int L = 0, s = 0, nch = 0;
+  int64_t nbox = 0, nleaf = 0;
+  std::vector<int64_t> level_off;  // host, size L+2
+
+  // tree (device)
+  int32_t* perm = nullptr;        // [n]
+  int32_t* leaf_start = nullptr;  // [nleaf+1]
+  double* xs = nullptr;           // leaf-ordered positions [n] x3 (SoA)
+  double* ys = nullptr;
+  double* zs = nullptr;
+  double* cx = nullptr;  // box centres [nbox] (SoA)
+  double* cy = nullptr;
+  double* cz = nullptr;
+  double* radius = nullptr;  // [nbox]
+  int32_t max_leaf_count = 0;
+
+  // lists (device), CSR by target
+  int32_t* m2l_ptr = nullptr;  // [nbox+1]
+  int32_t* m2l_src = nullptr;  // [n_m2l]
+  int32_t* p2p_ptr = nullptr;  // [nleaf+1]
+  int32_t* p2p_src = nullptr;  // [n_p2p]
+  // M2L work items: item i covers pairs [item_begin[i], item_end[i]) of
+  // target item_tgt[i]; items of one target are consecutive and
+  // item_ptr[t]..item_ptr[t+1] lists them.
+  int32_t* item_tgt = nullptr;
+  int32_t* item_begin = nullptr;
+  int32_t* item_end = nullptr;
+  int32_t* item_ptr = nullptr;  // [nbox+1]
+  int64_t n_items = 0;
+  int64_t n_m2l = 0, n_p2p = 0, p2p_inter = 0;
+
+  // evaluation workspace
+  void* q_leaf = nullptr;    // [max_rhs][n]
+  void* C = nullptr;         // [nbox][K]   multipoles (normalised)
+  void* D = nullptr;         // [nbox][K]   locals (normalised)
+  void* partial = nullptr;   // [n_items][K] M2L partial sums
+  const void* tables = nullptr;  // device operator tables for (p, precision)
+
+  std::vector<fmm::DevBuf> bufs;
+  size_t device_bytes = 0;
+};
+
+namespace fmm {
+
+void* plan_alloc(fmm_plan* pl, size_t bytes);
+void plan_free_all(fmm_plan* pl);
+
+// Tree build (tree.hip): fills perm, leaf_start, xs/ys/zs, centres, radii.
+void build_tree(fmm_plan* pl, const double* pos, hipStream_t st);
+// Lists (lists.hip): fills m2l_*, p2p_*, items.
+void build_lists(fmm_plan* pl, hipStream_t st);
+// Operator tables for order p (tables.cpp), cached per process/device.
+const void* get_tables(int p, int precision, int device);
+// Evaluation (eval.hip).
+void evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot, void* field,
+              hipStream_t st);
+
+// Sorting primitives (sort.hip).
+size_t sort_pairs_u64_i32_temp(int n);
+void sort_pairs_u64_i32(void* temp, size_t temp_bytes, const uint64_t* kin,
+                        uint64_t* kout, const int32_t* vin, int32_t* vout,
+                        int n, hipStream_t st);
+size_t sort_keys_u64_temp(int64_t n);
+void sort_keys_u64(void* temp, size_t temp_bytes, const uint64_t* kin,
+                   uint64_t* kout, int64_t n, int end_bit, hipStream_t st);
+size_t scan_i32_temp(int64_t n);
+void exclusive_scan_i32(void* temp, size_t temp_bytes, const int32_t* in,
+                        int32_t* out, int64_t n, hipStream_t st);
+
+}  // namespace fmm

@@ -144,6 +144,34 @@ fmm_status fmm_plan_get_lists(const fmm_plan* plan, int64_t* m2l_src,
                               int64_t* m2l_tgt, int64_t* p2p_src,
                               int64_t* p2p_tgt);
 
+/* Direct summation of the potential (and field) at selected points, the
+ * reference the paper measures FMM errors against (Sec. III.A; eqs. 1-3):
+ *   pos      device, double[n][3], all sources
+ *   q        device, [n] double (FMM_FP64) or float (FMM_FP32)
+ *   targets  device, int64[ntargets] indices into pos, or NULL for all n
+ *            points (then ntargets must equal n)
+ *   pot      device, [ntargets] of the charge type
+ *   field    device, [ntargets][3] (-grad u) or NULL
+ * Pairs at distance 0 are skipped.  O(n * ntargets) work, enqueued on
+ * `stream`.  Errors: FMM_EINVAL (NULL, sizes, precision), FMM_EDEVICE. */
+fmm_status fmm_direct(const double* pos, int64_t n, const void* q, int precision,
+                      const int64_t* targets, int64_t ntargets, void* pot,
+                      void* field, void* stream);
+
+/* Per-stage timing of evaluations, the breakdown of the paper's Fig. 5
+ * (Sec. III.A: sort, mpls, M2M, M2L, L2L, evloc, evdir).  Stage indices:
+ *   0 sort (charges to leaf order), 1 P2M, 2 M2M, 3 M2L, 4 L2L,
+ *   5 L2P (evloc), 6 P2P (evdir).
+ * While enabled, every fmm_evaluate records HIP events on its stream
+ * around each stage.  fmm_plan_read_profile waits for those events, writes
+ * the summed milliseconds per stage to stage_ms[FMM_NSTAGES] (host) and the
+ * number of evaluated passes (charge vectors) to *passes, and clears the
+ * record.  Disabling also clears it. */
+#define FMM_NSTAGES 7
+fmm_status fmm_plan_set_profiling(fmm_plan* plan, int enable);
+fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
+                                 int64_t* passes);
+
 /* Release the plan and its device memory (NULL is accepted). */
 fmm_status fmm_plan_destroy(fmm_plan* plan);
 

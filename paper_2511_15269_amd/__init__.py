@@ -16,10 +16,34 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (FMM_FP32, FMM_FP64, FMM_TIE_SOURCE, FMM_TIE_TARGET, FMMError,
-                   FmmParams, FmmPlanInfo, check, lib)
+from ._lib import (FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
+                   STAGES, FMMError, FmmParams, FmmPlanInfo, check, lib)
 
-__all__ = ["Plan", "FMMError", "params"]
+__all__ = ["Plan", "FMMError", "params", "direct", "STAGES"]
+
+
+def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = None,
+           field: bool = True, stream=None):
+    """Direct-sum potential (and field) at ``targets`` (int64 indices into
+    pos, CUDA) or at every point; runs in the library's direct kernel."""
+    if not (pos.is_cuda and q.is_cuda):
+        raise ValueError("pos and q must be CUDA tensors")
+    pos = pos.to(torch.float64).contiguous()
+    q = q.contiguous()
+    prec = FMM_FP64 if q.dtype == torch.float64 else FMM_FP32
+    n = pos.shape[0]
+    nt = n if targets is None else targets.numel()
+    if targets is not None:
+        targets = targets.to(device=pos.device, dtype=torch.int64).contiguous()
+    pot = torch.empty(nt, dtype=q.dtype, device=q.device)
+    fld = torch.empty((nt, 3), dtype=q.dtype, device=q.device) if field else None
+    with torch.cuda.device(pos.device):
+        check(lib().fmm_direct(ctypes.c_void_p(pos.data_ptr()), n, ctypes.c_void_p(q.data_ptr()),
+                               prec, ctypes.c_void_p(targets.data_ptr()) if targets is not None else None,
+                               nt, ctypes.c_void_p(pot.data_ptr()),
+                               ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
+                               _stream_ptr(stream)))
+    return pot, fld
 
 
 def params(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16,
@@ -96,6 +120,20 @@ class Plan:
         if single:
             return pot[0], (fld[0] if fld is not None else None)
         return pot, fld
+
+    def set_profiling(self, on: bool = True) -> None:
+        """Record per-stage HIP events in every evaluate (see
+        read_profile)."""
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_set_profiling(self._h, 1 if on else 0))
+
+    def read_profile(self) -> tuple[dict, int]:
+        """({stage: summed ms}, passes) since the last read; clears."""
+        ms = (ctypes.c_double * FMM_NSTAGES)()
+        passes = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_read_profile(self._h, ms, ctypes.byref(passes)))
+        return {k: ms[i] for i, k in enumerate(STAGES)}, passes.value
 
     def tree(self):
         """(perm, leaf_start, centre[B,3], radius[B]) as numpy arrays."""

@@ -12,6 +12,8 @@ STATUS_NAMES = {0: "FMM_OK", 1: "FMM_EINVAL", 2: "FMM_ENOMEM", 3: "FMM_EDEVICE",
                 4: "FMM_ENOTSUP", 5: "FMM_ESTATE"}
 FMM_FP64, FMM_FP32 = 0, 1
 FMM_TIE_SOURCE, FMM_TIE_TARGET = 0, 1
+FMM_NSTAGES = 7
+STAGES = ("sort", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 
 
 class FmmParams(ctypes.Structure):
@@ -55,8 +57,12 @@ def lib() -> ctypes.CDLL:
         L.fmm_plan_get_tree.argtypes = [vp, i64p, i64p, dp, dp]
         L.fmm_plan_get_lists.argtypes = [vp, i64p, i64p, i64p, i64p]
         L.fmm_plan_destroy.argtypes = [vp]
+        L.fmm_direct.argtypes = [vp, i64, vp, ctypes.c_int, vp, i64, vp, vp, vp]
+        L.fmm_plan_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.fmm_plan_read_profile.argtypes = [vp, dp, i64p]
         for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
-                  "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy"):
+                  "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy",
+                  "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

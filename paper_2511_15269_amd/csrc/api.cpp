@@ -31,6 +31,23 @@ void* plan_alloc(fmm_plan* pl, size_t bytes) {
   return p;
 }
 
+hipEvent_t take_event(fmm_plan* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  FMM_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void release_profile(fmm_plan* pl) {
+  for (auto& row : pl->ev_rows)
+    for (hipEvent_t e : row) pl->ev_pool.push_back(e);
+  pl->ev_rows.clear();
+}
+
 void plan_free_all(fmm_plan* pl) {
   for (auto& b : pl->bufs) (void)hipFree(b.ptr);
   pl->bufs.clear();
@@ -139,7 +156,7 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
       build_lists(pl.get(), st);
       const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
       const size_t K = (size_t)ncoef(prm->p);
-      pl->q_leaf = plan_alloc(pl.get(), es * (size_t)n);
+      pl->src = plan_alloc(pl.get(), 32 * (size_t)n);
       pl->C = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
       pl->D = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
       pl->partial = plan_alloc(pl.get(), es * K * (size_t)std::max<int64_t>(pl->n_items, 1));
@@ -242,11 +259,57 @@ fmm_status fmm_plan_get_lists(const fmm_plan* pl, int64_t* m2l_src, int64_t* m2l
   });
 }
 
+fmm_status fmm_direct(const double* pos, int64_t n, const void* q, int precision,
+                      const int64_t* targets, int64_t ntargets, void* pot, void* field,
+                      void* stream) {
+  return guard([&] {
+    if (!pos || !q || !pot) throw Error{FMM_EINVAL, "pos, q and pot must not be NULL"};
+    if (n < 1 || ntargets < 0) throw Error{FMM_EINVAL, "bad sizes"};
+    if (!targets && ntargets != n) throw Error{FMM_EINVAL, "ntargets must equal n without targets"};
+    if (precision != FMM_FP64 && precision != FMM_FP32) throw Error{FMM_EINVAL, "bad precision"};
+    direct_sum(n, pos, q, precision, targets, ntargets, pot, field, (hipStream_t)stream);
+  });
+}
+
+fmm_status fmm_plan_set_profiling(fmm_plan* pl, int enable) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    check_device(pl);
+    pl->profiling = enable != 0;
+    if (!enable) {
+      for (auto& row : pl->ev_rows)
+        for (hipEvent_t e : row) FMM_HIP(hipEventSynchronize(e));
+      release_profile(pl);
+    }
+  });
+}
+
+fmm_status fmm_plan_read_profile(fmm_plan* pl, double* stage_ms, int64_t* passes) {
+  return guard([&] {
+    if (!pl || !stage_ms) throw Error{FMM_EINVAL, "NULL argument"};
+    check_device(pl);
+    double acc[FMM_NSTAGES] = {0};
+    for (auto& row : pl->ev_rows) {
+      FMM_HIP(hipEventSynchronize(row.back()));
+      for (int k = 0; k < FMM_NSTAGES; ++k) {
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, row[k], row[k + 1]));
+        acc[k] += ms;
+      }
+    }
+    for (int k = 0; k < FMM_NSTAGES; ++k) stage_ms[k] = acc[k];
+    if (passes) *passes = (int64_t)pl->ev_rows.size();
+    release_profile(pl);
+  });
+}
+
 fmm_status fmm_plan_destroy(fmm_plan* pl) {
   return guard([&] {
     if (!pl) return;
     (void)hipSetDevice(pl->device);
     (void)hipDeviceSynchronize();
+    release_profile(pl);
+    for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
     plan_free_all(pl);
     delete pl;
   });

@@ -23,8 +23,10 @@
 //   L2L:      thread = box of the level; adds its M2L partials and the
 //             shifted local expansion of its parent.
 //   P2M:      block = leaf, thread = point, LDS reduction over points.
-//   L2P+P2P:  block = target leaf, thread = target point; the source
-//             leaves of the direct list are read with wave-uniform loads.
+//   L2P:      block = target leaf, thread = target point; writes outputs.
+//   P2P:      block = target leaf, thread = target point; adds the near
+//             field; the source points of the direct list are read with
+//             wave-uniform (scalar) loads.
 #include <cmath>
 
 #include "internal.h"
@@ -215,6 +217,12 @@ __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double 
     azimuth<P, T, +1, 1>(v, am_c, am_s);
 }
 
+// Source point in leaf order with its charge, read by P2M and P2P (one
+// 32-byte record, so that a wave-uniform read is a single scalar load).
+struct alignas(32) Src {
+  double x, y, z, q;
+};
+
 // ---------------------------------------------------------------- P2M
 // Regular basis R-hat^m_n(x, y, z) in degree-major order by the App. A.1
 // recursions; calls f(k, value) for k = 0..K-1 as values become available.
@@ -260,10 +268,9 @@ __device__ __forceinline__ void regular_basis(T x, T y, T z, F&& f) {
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(
     int nleaf, int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
-    const double* __restrict__ xs, const double* __restrict__ ys,
-    const double* __restrict__ zs, const T* __restrict__ q,
-    const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const T* __restrict__ tab, T* __restrict__ C) {
+    const Src* __restrict__ src, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const T* __restrict__ tab, T* __restrict__ C) {
   constexpr int K = K_<P>::value;
   __shared__ T red[K][65];
   const int leaf = blockIdx.x;
@@ -275,8 +282,9 @@ __global__ __launch_bounds__(64) void k_p2m(
   for (int k = 0; k < K; ++k) acc[k] = T(0);
   const double ox = cx[g], oy = cy[g], oz = cz[g];
   for (int j = st + lane; j < en; j += 64) {
-    const T qj = q[j];
-    regular_basis<P, T>(T(xs[j] - ox), T(ys[j] - oy), T(zs[j] - oz),
+    const Src a = src[j];
+    const T qj = T(a.q);
+    regular_basis<P, T>(T(a.x - ox), T(a.y - oy), T(a.z - oz),
                         [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
   }
 #pragma unroll
@@ -462,23 +470,21 @@ __device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ 
 }
 
 __device__ __forceinline__ double inv_sqrt(double r2) {
-  double y = __builtin_amdgcn_rsq(r2);
-  y = y * (1.5 - 0.5 * r2 * y * y);
-  y = y * (1.5 - 0.5 * r2 * y * y);
-  return y;
+  // hardware estimate refined by one Newton step
+  const double y = __builtin_amdgcn_rsq(r2);
+  return y * fma(-0.5 * r2, y * y, 1.5);
 }
 __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+// L2P: u = -1/(4 pi) sum w_m D R-hat, field = -grad u, at every point of the
+// target leaf; writes (not adds) the outputs in input order.
 template <int P, typename T, bool FIELD>
-__global__ __launch_bounds__(64) void k_l2p_p2p(
+__global__ __launch_bounds__(64) void k_l2p(
     int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
-    const int32_t* __restrict__ perm, const double* __restrict__ xs,
-    const double* __restrict__ ys, const double* __restrict__ zs,
-    const T* __restrict__ q, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
-    const T* __restrict__ D, const int32_t* __restrict__ p2p_ptr,
-    const int32_t* __restrict__ p2p_src, const T* __restrict__ tab,
-    T* __restrict__ pot, T* __restrict__ field) {
+    const int32_t* __restrict__ perm, const Src* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const T* __restrict__ D,
+    const T* __restrict__ tab, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int K = K_<P>::value;
   __shared__ T w[K];
   const int leaf = blockIdx.x;
@@ -488,50 +494,92 @@ __global__ __launch_bounds__(64) void k_l2p_p2p(
   __syncthreads();
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g];
-  const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
-  for (int i = st + lane; i - lane < en; i += 64) {
-    const bool live = i < en;
-    const int ii = live ? i : st;
-    const double xi = xs[ii], yi = ys[ii], zi = zs[ii];
+  for (int i = st + lane; i < en; i += 64) {
+    const Src a = src[i];
     T fp = T(0), fx = T(0), fy = T(0), fz = T(0);
-    local_eval<P, T>(T(xi - ox), T(yi - oy), T(zi - oz), w, fp, fx, fy, fz);
-    // near field: sum q/r and q (xi - xj)/r^3 over the direct list
-    T np_ = T(0), nx = T(0), ny = T(0), nz = T(0);
+    local_eval<P, T>(T(a.x - ox), T(a.y - oy), T(a.z - oz), w, fp, fx, fy, fz);
+    const int o = perm[i];
+    pot[o] = -T(kInv4Pi) * fp;
+    if (FIELD) {
+      field[3 * (int64_t)o + 0] = T(kInv4Pi) * fx;
+      field[3 * (int64_t)o + 1] = T(kInv4Pi) * fy;
+      field[3 * (int64_t)o + 2] = T(kInv4Pi) * fz;
+    }
+  }
+}
+
+// P2P: adds -1/(4 pi) sum q/r and the matching field over the direct list.
+// Block = target leaf, lane = target point; all lanes walk the same source
+// points, so each source record is one wave-uniform (scalar) load, fetched
+// in chunks of kChunk.
+constexpr int kChunk = 8;
+
+template <typename T, bool FIELD>
+__device__ __forceinline__ void p2p_pair(const Src& s, double xi, double yi, double zi,
+                                         T& u, T& gx, T& gy, T& gz) {
+  const T dx = T(xi - s.x), dy = T(yi - s.y), dz = T(zi - s.z);
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  const T inv0 = inv_sqrt(r2);
+  const T inv = r2 > T(0) ? inv0 : T(0);  // distance 0 contributes nothing
+  const T qi = T(s.q) * inv;
+  u += qi;
+  if (FIELD) {
+    const T q3 = qi * inv * inv;
+    gx = fma(q3, dx, gx);
+    gy = fma(q3, dy, gy);
+    gz = fma(q3, dz, gz);
+  }
+}
+
+template <typename T, bool FIELD>
+__global__ __launch_bounds__(64) void k_p2p(
+    const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
+    const Src* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
+    const int32_t* __restrict__ p2p_src, T* __restrict__ pot,
+    T* __restrict__ field) {
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
+  const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
+  for (int i0 = st; i0 < en; i0 += 64) {
+    const int i = i0 + lane;
+    const bool live = i < en;
+    const Src a = src[live ? i : st];
+    T u = T(0), gx = T(0), gy = T(0), gz = T(0);
     for (int k = pb; k < pe; ++k) {
       const int sl = p2p_src[k];
       const int js = leaf_start[sl], je = leaf_start[sl + 1];
-      for (int j = js; j < je; ++j) {
-        const T dx = T(xi - xs[j]), dy = T(yi - ys[j]), dz = T(zi - zs[j]);
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T inv = r2 > T(0) ? inv_sqrt(r2) : T(0);
-        const T qi = q[j] * inv;
-        np_ += qi;
-        if (FIELD) {
-          const T q3 = qi * inv * inv;
-          nx = fma(q3, dx, nx);
-          ny = fma(q3, dy, ny);
-          nz = fma(q3, dz, nz);
-        }
+      int j = js;
+      for (; j + kChunk <= je; j += kChunk) {
+        Src c[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) c[t] = src[j + t];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(c[t], a.x, a.y, a.z, u, gx, gy, gz);
       }
+      for (; j < je; ++j) p2p_pair<T, FIELD>(src[j], a.x, a.y, a.z, u, gx, gy, gz);
     }
     if (live) {
       const int o = perm[i];
-      // u = -1/(4 pi) (far sum + near sum);  field = -grad u
-      pot[o] = -T(kInv4Pi) * (fp + np_);
+      pot[o] += -T(kInv4Pi) * u;
       if (FIELD) {
-        field[3 * (int64_t)o + 0] = T(kInv4Pi) * (fx - nx);
-        field[3 * (int64_t)o + 1] = T(kInv4Pi) * (fy - ny);
-        field[3 * (int64_t)o + 2] = T(kInv4Pi) * (fz - nz);
+        // field = -grad u;  grad of the near part is +(1/4pi) sum q d/r^3
+        field[3 * (int64_t)o + 0] -= T(kInv4Pi) * gx;
+        field[3 * (int64_t)o + 1] -= T(kInv4Pi) * gy;
+        field[3 * (int64_t)o + 2] -= T(kInv4Pi) * gz;
       }
     }
   }
 }
 
+// sort stage: sources in leaf order with their charges
 template <typename T>
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm,
-                         const T* __restrict__ q, T* __restrict__ ql) {
+                         const double* __restrict__ xs, const double* __restrict__ ys,
+                         const double* __restrict__ zs, const T* __restrict__ q,
+                         Src* __restrict__ src) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) ql[j] = q[perm[j]];
+  if (j < n) src[j] = Src{xs[j], ys[j], zs[j], double(q[perm[j]])};
 }
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -541,40 +589,60 @@ void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
   constexpr int K = K_<P>::value;
   const int L = pl->L, s = pl->s;
   const T* tab = (const T*)pl->tables;
-  T* ql = (T*)pl->q_leaf;
+  Src* src = (Src*)pl->src;
   T* C = (T*)pl->C;
   T* D = (T*)pl->D;
   T* part = (T*)pl->partial;
   const int64_t n = pl->n;
   const int64_t leaf0 = pl->level_off[L];
-  k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, q, ql);
-  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-      (int)pl->nleaf, leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs, ql, pl->cx,
-      pl->cy, pl->cz, tab, C);
+  std::vector<hipEvent_t>* row = nullptr;
+  if (pl->profiling) {
+    pl->ev_rows.emplace_back();
+    row = &pl->ev_rows.back();
+    for (int k = 0; k <= FMM_NSTAGES; ++k) row->push_back(take_event(pl));
+  }
+  auto mark = [&](int k) {
+    if (row) FMM_HIP(hipEventRecord((*row)[k], st));
+  };
+  mark(0);
+  k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
+  mark(1);
+  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>((int)pl->nleaf, leaf0, pl->leaf_start,
+                                                  src, pl->cx, pl->cy, pl->cz, tab, C);
+  mark(2);
   for (int l = L - 1; l >= 0; --l) {
     const int64_t nchild = pl->level_off[l + 2] - pl->level_off[l + 1];
     k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(
         nchild, pl->level_off[l + 1], pl->level_off[l], s, pl->cx, pl->cy,
         pl->cz, tab, C);
   }
+  mark(3);
   if (pl->n_items > 0)
     k_m2l<P, T><<<blocks(pl->n_items, kM2LThreads), kM2LThreads, 0, st>>>(
         pl->n_items, pl->item_tgt, pl->item_begin, pl->item_end, pl->m2l_src,
         pl->cx, pl->cy, pl->cz, C, tab, part);
+  mark(4);
   for (int l = 0; l <= L; ++l) {
     const int64_t nb = pl->level_off[l + 1] - pl->level_off[l];
     k_l2l<P, T><<<blocks(nb, 64), 64, 0, st>>>(
         nb, pl->level_off[l], l > 0 ? pl->level_off[l - 1] : -1, s,
         pl->item_ptr, part, pl->cx, pl->cy, pl->cz, tab, D);
   }
+  mark(5);
   if (field)
-    k_l2p_p2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, ql, pl->cx,
-        pl->cy, pl->cz, D, pl->p2p_ptr, pl->p2p_src, tab, pot, field);
+    k_l2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        leaf0, pl->leaf_start, pl->perm, src, pl->cx, pl->cy, pl->cz, D, tab, pot, field);
   else
-    k_l2p_p2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, ql, pl->cx,
-        pl->cy, pl->cz, D, pl->p2p_ptr, pl->p2p_src, tab, pot, field);
+    k_l2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        leaf0, pl->leaf_start, pl->perm, src, pl->cx, pl->cy, pl->cz, D, tab, pot, field);
+  mark(6);
+  if (field)
+    k_p2p<T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        pl->leaf_start, pl->perm, src, pl->p2p_ptr, pl->p2p_src, pot, field);
+  else
+    k_p2p<T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
+        pl->leaf_start, pl->perm, src, pl->p2p_ptr, pl->p2p_src, pot, field);
+  mark(7);
   FMM_HIP(hipGetLastError());
   (void)K;
 }

@@ -83,7 +83,7 @@ struct fmm_plan {
   int64_t n_m2l = 0, n_p2p = 0, p2p_inter = 0;
 
   // evaluation workspace
-  void* q_leaf = nullptr;    // [max_rhs][n]
+  void* src = nullptr;       // [n] {x, y, z, q} in leaf order
   void* C = nullptr;         // [nbox][K]   multipoles (normalised)
   void* D = nullptr;         // [nbox][K]   locals (normalised)
   void* partial = nullptr;   // [n_items][K] M2L partial sums
@@ -91,6 +91,11 @@ struct fmm_plan {
 
   std::vector<fmm::DevBuf> bufs;
   size_t device_bytes = 0;
+
+  // stage timing (fmm_plan_set_profiling)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;               // free events
+  std::vector<std::vector<hipEvent_t>> ev_rows;  // FMM_NSTAGES+1 per pass
 };
 
 namespace fmm {
@@ -107,6 +112,14 @@ const void* get_tables(int p, int precision, int device);
 // Evaluation (eval.hip).
 void evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot, void* field,
               hipStream_t st);
+
+// Direct summation (direct.hip).
+void direct_sum(int64_t n, const double* pos, const void* q, int precision,
+                const int64_t* targets, int64_t nt, void* pot, void* field,
+                hipStream_t st);
+// Stage-timing helpers (api.cpp).
+hipEvent_t take_event(fmm_plan* pl);
+void release_profile(fmm_plan* pl);
 
 // Sorting primitives (sort.hip).
 size_t sort_pairs_u64_i32_temp(int n);

@@ -157,3 +157,36 @@ def test_bad_inputs_raise(fmm):
         plan.evaluate(torch.stack([qt, qt]))  # nrhs above the plan's max_rhs
     u, f = plan.evaluate(qt)  # the plan still works
     assert torch.isfinite(u).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_direct_kernel_matches_oracle_direct(fmm, prec):
+    from oracle.direct import direct
+    _say(f"[direct kernel] {prec}")
+    pos, q = workloads.uniform_cube(3000, 6)
+    pos[5] = pos[9]  # a coincident pair contributes nothing
+    tg = np.array([0, 5, 9, 17, 2999])
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u, f = fmm.direct(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda().to(dt),
+                      torch.from_numpy(tg).cuda())
+    ud, gd = direct(pos, q, pos[tg], field=True)
+    tol = 1e-13 if prec == "fp64" else 1e-5
+    assert _rel(u.double().cpu().numpy(), ud) <= tol
+    assert _rel(f.double().cpu().numpy(), -gd) <= tol
+    ua, fa = fmm.direct(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda().to(dt))
+    ud, gd = direct(pos, q, field=True)
+    assert _rel(ua.double().cpu().numpy(), ud) <= tol
+
+
+def test_stage_profile_counts_passes(fmm):
+    pos, q = workloads.uniform_cube(20000, 7)
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=6, leaf_max=64, splits=2, theta=0.6)
+    qt = torch.from_numpy(q).cuda()
+    plan.set_profiling(True)
+    for _ in range(3):
+        plan.evaluate(qt)
+    ms, passes = plan.read_profile()
+    assert passes == 3 and all(v >= 0.0 for v in ms.values()) and ms["p2p"] > 0.0
+    _, passes = plan.read_profile()
+    assert passes == 0
+    plan.set_profiling(False)

@@ -85,8 +85,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=128)
-    ap.add_argument("--splits", type=int, default=2)
-    ap.add_argument("--theta", type=float, default=0.6)
+    ap.add_argument("--splits", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.7)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--samples", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -43,6 +43,18 @@ struct K_ {
   static constexpr int value = (P + 1) * (P + 1);
 };
 
+// Opaque copy of a wave-uniform pointer: table reads through it are issued
+// where they are used instead of being hoisted out of the interaction loop
+// (hoisting them all would exceed the scalar register file and spill).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;  // constant memory
+
+template <typename T>
+__device__ __forceinline__ cptr<T> local_ptr(const T* p) {
+  asm volatile("" : "+s"(p));
+  return (cptr<T>)p;
+}
+
 // cos(m g), sin(m g), m = 0..P, by repeated complex multiplication
 template <int P, typename T>
 __device__ __forceinline__ void powers(T c1, T s1, T* c, T* s) {
@@ -85,24 +97,22 @@ __device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
   }
 }
 
-// v_n <- Y_n v_n (TR: Y_n^T v_n); zero entries are skipped at compile time
+// v_n <- Y_n v_n (TR: Y_n^T v_n) over the stored nonzero entries
 template <int P, bool TR, typename T>
 __device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
-    const T* Y = tab + tab_y(P) + ybase(n);
-    const int w = 2 * n + 1;
+    cptr<T> Y = local_ptr(tab) + (TR ? tab_yt(P) : tab_y(P)) + ycbase(n);
     T u[2 * P + 1];
+    int o = 0;
 #pragma unroll
     for (int a = -n; a <= n; ++a) {
       T acc = T(0);
 #pragma unroll
       for (int b = -n; b <= n; ++b) {
-        if ((a >= 0) != (b >= 0)) continue;
-        const int par = ((a < 0 ? -a : a) + (b < 0 ? -b : b) + n) & 1;
-        if ((a >= 0 && par) || (a < 0 && !par)) continue;
-        const T y = TR ? Y[(b + n) * w + (a + n)] : Y[(a + n) * w + (b + n)];
-        acc = fma(y, v[cidx(n, b)], acc);
+        if (!ynz(n, a, b)) continue;
+        acc = fma(Y[o], v[cidx(n, b)], acc);
+        ++o;
       }
       u[a + n] = acc;
     }
@@ -129,13 +139,14 @@ __device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
+      cptr<T> tb = local_ptr(tab) + tab_tm2l(P) + zl_base(P, am);
       T o[P + 1];
+      int c = 0;
 #pragma unroll
       for (int n = am; n <= P; ++n) {
         T acc = T(0);
 #pragma unroll
-        for (int k = am; k <= P; ++k)
-          acc = fma(tab[tab_tm2l(P) + t3(P, n, k, am)], v[cidx(k, m)], acc);
+        for (int k = am; k <= P; ++k) acc = fma(tb[c++], v[cidx(k, m)], acc);
         o[n] = acc * ip[n + 1];
       }
 #pragma unroll
@@ -149,18 +160,18 @@ __device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
+      cptr<T> tb = local_ptr(tab) + (KIND == kM2M ? tab_tm2m(P) : tab_tl2l(P)) + zt_base(P, am);
       T o[P + 1];
+      int c = 0;
 #pragma unroll
       for (int n = am; n <= P; ++n) {
         T acc = T(0);
         if (KIND == kM2M) {
 #pragma unroll
-          for (int k = am; k <= n; ++k)
-            acc = fma(tab[tab_tm2m(P) + t3(P, n, k, am)] * pw[n - k], v[cidx(k, m)], acc);
+          for (int k = am; k <= n; ++k) acc = fma(tb[c++] * pw[n - k], v[cidx(k, m)], acc);
         } else {
 #pragma unroll
-          for (int k = n; k <= P; ++k)
-            acc = fma(tab[tab_tl2l(P) + t3(P, n, k, am)] * pw[k - n], v[cidx(k, m)], acc);
+          for (int k = n; k <= P; ++k) acc = fma(tb[c++] * pw[k - n], v[cidx(k, m)], acc);
         }
         o[n] = acc;
       }
@@ -531,35 +542,55 @@ __device__ __forceinline__ void p2p_pair(const Src& s, double xi, double yi, dou
   }
 }
 
-template <typename T, bool FIELD>
+// G source groups: lanes [g*64/G, (g+1)*64/G) share targets with the
+// other groups but walk every G-th source point starting at point g.  G = 1
+// keeps all source reads wave-uniform (scalar loads); G = 2, 4 fill the
+// wave when leaves hold at most 32 or 16 points.  Group sums are combined
+// with cross-lane shuffles in a fixed order.
+template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
     const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
     const Src* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
     const int32_t* __restrict__ p2p_src, T* __restrict__ pot,
     T* __restrict__ field) {
+  constexpr int TL = 64 / G;  // targets per pass
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
+  const int g = lane / TL;
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
-  for (int i0 = st; i0 < en; i0 += 64) {
-    const int i = i0 + lane;
+  for (int i0 = st; i0 < en; i0 += TL) {
+    const int i = i0 + lane % TL;
     const bool live = i < en;
     const Src a = src[live ? i : st];
     T u = T(0), gx = T(0), gy = T(0), gz = T(0);
     for (int k = pb; k < pe; ++k) {
       const int sl = p2p_src[k];
-      const int js = leaf_start[sl], je = leaf_start[sl + 1];
-      int j = js;
-      for (; j + kChunk <= je; j += kChunk) {
-        Src c[kChunk];
+      const int js = leaf_start[sl], cnt = leaf_start[sl + 1] - js;
+      const int full = cnt / G;  // points per group present in every group
+      const Src* base = src + js + g;
+      int c = 0;
+      for (; c + kChunk <= full; c += kChunk) {
+        Src r[kChunk];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) c[t] = src[j + t];
+        for (int t = 0; t < kChunk; ++t) r[t] = base[(c + t) * G];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(c[t], a.x, a.y, a.z, u, gx, gy, gz);
+        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, u, gx, gy, gz);
       }
-      for (; j < je; ++j) p2p_pair<T, FIELD>(src[j], a.x, a.y, a.z, u, gx, gy, gz);
+      for (; c < full; ++c) p2p_pair<T, FIELD>(base[c * G], a.x, a.y, a.z, u, gx, gy, gz);
+      if (G > 1 && g < cnt - full * G)
+        p2p_pair<T, FIELD>(base[full * G], a.x, a.y, a.z, u, gx, gy, gz);
     }
-    if (live) {
+#pragma unroll
+    for (int off = TL; off < 64; off <<= 1) {
+      u += __shfl_xor(u, off, 64);
+      if (FIELD) {
+        gx += __shfl_xor(gx, off, 64);
+        gy += __shfl_xor(gy, off, 64);
+        gz += __shfl_xor(gz, off, 64);
+      }
+    }
+    if (live && g == 0) {
       const int o = perm[i];
       pot[o] += -T(kInv4Pi) * u;
       if (FIELD) {
@@ -636,12 +667,20 @@ void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
     k_l2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
         leaf0, pl->leaf_start, pl->perm, src, pl->cx, pl->cy, pl->cz, D, tab, pot, field);
   mark(6);
-  if (field)
-    k_p2p<T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        pl->leaf_start, pl->perm, src, pl->p2p_ptr, pl->p2p_src, pot, field);
-  else
-    k_p2p<T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        pl->leaf_start, pl->perm, src, pl->p2p_ptr, pl->p2p_src, pot, field);
+  const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
+  auto p2p = [&](auto kern) {
+    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, pl->p2p_ptr,
+                                              pl->p2p_src, pot, field);
+  };
+  if (field) {
+    if (G == 1) p2p(k_p2p<T, true, 1>);
+    else if (G == 2) p2p(k_p2p<T, true, 2>);
+    else p2p(k_p2p<T, true, 4>);
+  } else {
+    if (G == 1) p2p(k_p2p<T, false, 1>);
+    else if (G == 2) p2p(k_p2p<T, false, 2>);
+    else p2p(k_p2p<T, false, 4>);
+  }
   mark(7);
   FMM_HIP(hipGetLastError());
   (void)K;

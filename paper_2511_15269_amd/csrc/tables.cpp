@@ -15,7 +15,8 @@
 //   Y(a,b)   = (-1)^a [(-1)^b d_{ab} + d_{a,-b}]     (cos block, a,b > 0)
 //   Y(-a,-b) = (-1)^a [(-1)^b d_{ab} - d_{a,-b}]     (sin block, a,b > 0)
 // and cos and sin blocks do not mix; entries vanish unless |a|+|b|+n is even
-// (cos block) or odd (sin block).
+// (cos block) or odd (sin block).  Only the nonzero entries are stored, in
+// the order the kernels read them (see tables.h).
 //
 // z-axis translations of length r (App. B.3), normalised:
 //   M2M  Ct^m_n += sum_{k=|m|}^{n} N_{n|m|}/(N_{k|m|} (n-k)!) r^{n-k} Ct^m_k
@@ -105,7 +106,7 @@ std::vector<double> build(int P) {
   for (int n = 0; n <= P; ++n) {
     auto D = [&](int a, int b) { return d[((size_t)n * W + a + P) * W + b + P]; };
     const int w = 2 * n + 1;
-    double* Y = &t[tab_y(P) + ybase(n)];
+    std::vector<double> Y((size_t)w * w, 0.0);
     auto at = [&](int a, int b) -> double& { return Y[(a + n) * w + (b + n)]; };
     at(0, 0) = D(0, 0);
     for (int a = 1; a <= n; ++a) {
@@ -118,18 +119,27 @@ std::vector<double> build(int P) {
         at(-a, -b) = sa * (sb * D(a, b) - D(a, -b));
       }
     }
+    int o = tab_y(P) + ycbase(n), ot = tab_yt(P) + ycbase(n);
+    for (int a = -n; a <= n; ++a)
+      for (int b = -n; b <= n; ++b)
+        if (ynz(n, a, b)) {
+          t[o++] = at(a, b);
+          t[ot++] = at(b, a);
+        }
   }
-  for (int n = 0; n <= P; ++n)
-    for (int k = 0; k <= P; ++k)
-      for (int m = 0; m <= std::min(n, k); ++m) {
-        double sg = ((k + m) % 2) ? -1.0 : 1.0;
-        t[tab_tm2l(P) + t3(P, n, k, m)] = sg * fact(n + k) / (Nnm(n, m) * Nnm(k, m));
-        if (k <= n)
-          t[tab_tm2m(P) + t3(P, n, k, m)] = Nnm(n, m) / (Nnm(k, m) * fact(n - k));
-        if (k >= n)
-          t[tab_tl2l(P) + t3(P, n, k, m)] =
-              (((k - n) % 2) ? -1.0 : 1.0) * Nnm(k, m) / (Nnm(n, m) * fact(k - n));
-      }
+  for (int am = 0; am <= P; ++am) {
+    int o = tab_tm2l(P) + zl_base(P, am);
+    for (int n = am; n <= P; ++n)
+      for (int k = am; k <= P; ++k)
+        t[o++] = (((k + am) % 2) ? -1.0 : 1.0) * fact(n + k) / (Nnm(n, am) * Nnm(k, am));
+    o = tab_tm2m(P) + zt_base(P, am);
+    for (int n = am; n <= P; ++n)
+      for (int k = am; k <= n; ++k) t[o++] = Nnm(n, am) / (Nnm(k, am) * fact(n - k));
+    o = tab_tl2l(P) + zt_base(P, am);
+    for (int n = am; n <= P; ++n)
+      for (int k = n; k <= P; ++k)
+        t[o++] = (((k - n) % 2) ? -1.0 : 1.0) * Nnm(k, am) / (Nnm(n, am) * fact(k - n));
+  }
   return t;
 }
 

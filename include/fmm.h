@@ -125,6 +125,33 @@ fmm_status fmm_plan_get_info(const fmm_plan* plan, fmm_plan_info* info);
 fmm_status fmm_evaluate(fmm_plan* plan, const void* q, int nrhs, void* pot,
                         void* field, void* stream);
 
+/* Transposed evaluation: the adjoint operator G-hat^T of fmm_evaluate's
+ * linear map q -> u-hat (tree, lists and centres frozen), i.e. the same FMM
+ * run over the transposed interaction lists (every M2L and P2P pair
+ * reversed).  Needed because the cross-level lists of Sec. II.B pair a
+ * source level with a different target level, so G-hat is not symmetric;
+ * the truncated two-centre kernel with the square truncation n, k <= p is
+ * symmetric under exchanging source and target with the shift reversed
+ * (App. B.3 operators), which makes the transposed-list FMM the exact
+ * transpose.  Arguments and errors as for fmm_evaluate. */
+fmm_status fmm_evaluate_transposed(fmm_plan* plan, const void* q, int nrhs,
+                                   void* pot, void* field, void* stream);
+
+/* Backward pass of u-hat = FMM(q, x) with frozen hierarchy, for upstream
+ * gradients g = dL/du-hat (autodiff of the evaluation, Sec. III.B):
+ *   grad_q = G-hat^T g
+ *   grad_x = g * grad u-hat(x) + q * grad (G-hat^T g)(x)   (per point, [n][3])
+ *   q          device [nrhs][n]: the charges of the forward pass
+ *   g          device [nrhs][n]
+ *   field_fwd  device [nrhs][n][3]: the field (-grad u-hat) of the forward pass
+ *   grad_q     device [nrhs][n] (written)
+ *   grad_x     device [nrhs][n][3] or NULL (then q and field_fwd may be NULL)
+ * For E = 1/2 q^T u-hat use g = q/2 and add u-hat/2 to grad_q.  Types follow
+ * the plan's precision.  Errors: FMM_EINVAL, FMM_EDEVICE. */
+fmm_status fmm_adjoint(fmm_plan* plan, const void* q, const void* g, int nrhs,
+                       const void* field_fwd, void* grad_q, void* grad_x,
+                       void* stream);
+
 /* Copy the tree to host buffers (any may be NULL):
  *   perm       int64[n]: leaf-ordered slot i holds input point perm[i]
  *   leaf_start int64[nleaf+1]: leaf j holds slots [leaf_start[j],

@@ -19,7 +19,7 @@ import torch
 from ._lib import (FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
                    STAGES, FMMError, FmmParams, FmmPlanInfo, check, lib)
 
-__all__ = ["Plan", "FMMError", "params", "direct", "STAGES"]
+__all__ = ["Plan", "FMMError", "params", "direct", "STAGES", "FMMPotential", "fmm_energy"]
 
 
 def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = None,
@@ -96,6 +96,51 @@ class Plan:
         check(lib().fmm_plan_get_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in FmmPlanInfo._fields_}
 
+    def _vec(self, x: torch.Tensor, name: str):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.dtype):
+            raise ValueError(f"{name} must be a CUDA {self.dtype} tensor")
+        xx = x.reshape(1, -1) if x.dim() == 1 else x
+        if xx.shape[1] != self.n:
+            raise ValueError(f"{name} has the wrong number of points")
+        return xx.contiguous()
+
+    def evaluate_transposed(self, q: torch.Tensor, field: bool = True, stream=None):
+        """The adjoint operator: G-hat^T q (and its field), same shapes as
+        evaluate."""
+        single = q.dim() == 1
+        qq = self._vec(q, "q")
+        R = qq.shape[0]
+        pot = torch.empty((R, self.n), dtype=self.dtype, device=q.device)
+        fld = torch.empty((R, self.n, 3), dtype=self.dtype, device=q.device) if field else None
+        with torch.cuda.device(self.device):
+            check(lib().fmm_evaluate_transposed(self._h, ctypes.c_void_p(qq.data_ptr()), R,
+                                                ctypes.c_void_p(pot.data_ptr()),
+                                                ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
+                                                _stream_ptr(stream)))
+        if single:
+            return pot[0], (fld[0] if fld is not None else None)
+        return pot, fld
+
+    def adjoint(self, q: torch.Tensor, g: torch.Tensor, field_fwd: torch.Tensor | None,
+                stream=None):
+        """(grad_q, grad_x) of sum g * u-hat(q, x) with the hierarchy frozen:
+        grad_q = G-hat^T g, grad_x = g grad u-hat + q grad(G-hat^T g)
+        (grad_x is None when field_fwd is None)."""
+        single = g.dim() == 1
+        gg = self._vec(g, "g")
+        R = gg.shape[0]
+        qq = self._vec(q, "q") if field_fwd is not None else None
+        ff = field_fwd.reshape(R, self.n, 3).contiguous() if field_fwd is not None else None
+        gq = torch.empty((R, self.n), dtype=self.dtype, device=g.device)
+        gx = torch.empty((R, self.n, 3), dtype=self.dtype, device=g.device) if ff is not None else None
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        with torch.cuda.device(self.device):
+            check(lib().fmm_adjoint(self._h, vp(qq), vp(gg), R, vp(ff), vp(gq), vp(gx),
+                                    _stream_ptr(stream)))
+        if single:
+            return gq[0], (gx[0] if gx is not None else None)
+        return gq, gx
+
     def evaluate(self, q: torch.Tensor, field: bool = True, out=None, stream=None):
         """Potentials (and fields = -grad u) for charges ``q`` ([N] or
         [R, N], CUDA, plan precision).  Returns (pot, field or None)."""
@@ -158,3 +203,31 @@ class Plan:
         with torch.cuda.device(self.device):
             check(lib().fmm_plan_get_lists(self._h, *[x.ctypes.data_as(P64) for x in a]))
         return tuple(a)
+
+
+class FMMPotential(torch.autograd.Function):
+    """u-hat = FMM(q, x) on a fixed plan, differentiable in q and in the
+    point positions x (hierarchy frozen: tree, lists and box centres do not
+    move).  ``pos`` must hold the positions the plan was built from."""
+
+    @staticmethod
+    def forward(ctx, q, pos, plan):
+        need_x = pos.requires_grad
+        u, f = plan.evaluate(q, field=need_x)
+        ctx.plan = plan
+        ctx.save_for_backward(q, f if need_x else None)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        q, f = ctx.saved_tensors
+        plan = ctx.plan
+        gq, gx = plan.adjoint(q, gu.contiguous(), f)
+        return gq, (gx.to(torch.float64) if gx is not None else None), None
+
+
+def fmm_energy(plan: Plan, q: torch.Tensor, pos: torch.Tensor) -> torch.Tensor:
+    """E = 1/2 sum_i q_i u-hat_i, differentiable in q and pos (frozen
+    hierarchy)."""
+    u = FMMPotential.apply(q, pos, plan)
+    return 0.5 * torch.dot(q, u)

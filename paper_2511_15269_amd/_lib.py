@@ -58,11 +58,14 @@ def lib() -> ctypes.CDLL:
         L.fmm_plan_get_lists.argtypes = [vp, i64p, i64p, i64p, i64p]
         L.fmm_plan_destroy.argtypes = [vp]
         L.fmm_direct.argtypes = [vp, i64, vp, ctypes.c_int, vp, i64, vp, vp, vp]
+        L.fmm_evaluate_transposed.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+        L.fmm_adjoint.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp, vp]
         L.fmm_plan_set_profiling.argtypes = [vp, ctypes.c_int]
         L.fmm_plan_read_profile.argtypes = [vp, dp, i64p]
         for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
                   "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy",
-                  "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile"):
+                  "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile",
+                  "fmm_evaluate_transposed", "fmm_adjoint"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

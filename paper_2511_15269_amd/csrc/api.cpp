@@ -152,6 +152,8 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
       pl->cy = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
       pl->cz = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
       pl->radius = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      pl->scale = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
+      pl->leaf_of = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * n);
       build_tree(pl.get(), pos, st);
       build_lists(pl.get(), st);
       const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
@@ -159,7 +161,11 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
       pl->src = plan_alloc(pl.get(), 32 * (size_t)n);
       pl->C = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
       pl->D = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
-      pl->partial = plan_alloc(pl.get(), es * K * (size_t)std::max<int64_t>(pl->n_items, 1));
+      pl->partial = plan_alloc(
+          pl.get(), es * K *
+                        (size_t)std::max<int64_t>(
+                            std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1));
+      pl->field_t = plan_alloc(pl.get(), es * 3 * (size_t)n);
       pl->tables = get_tables(prm->p, prm->precision, pl->device);
       FMM_HIP(hipStreamSynchronize(st));
     } catch (...) {
@@ -180,8 +186,8 @@ fmm_status fmm_plan_get_info(const fmm_plan* pl, fmm_plan_info* info) {
     r.splits = pl->s;
     r.nbox = pl->nbox;
     r.nleaf = pl->nleaf;
-    r.n_m2l = pl->n_m2l;
-    r.n_p2p = pl->n_p2p;
+    r.n_m2l = pl->lists[0].n_m2l;
+    r.n_p2p = pl->lists[0].n_p2p;
     r.p2p_interactions = pl->p2p_inter;
     r.device_bytes = (int64_t)pl->device_bytes;
     *info = r;
@@ -195,7 +201,40 @@ fmm_status fmm_evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot,
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
-    fmm::evaluate(pl, q, nrhs, pot, field, (hipStream_t)stream);
+    fmm::evaluate(pl, 0, q, nrhs, pot, field, (hipStream_t)stream);
+  });
+}
+
+fmm_status fmm_evaluate_transposed(fmm_plan* pl, const void* q, int nrhs, void* pot,
+                                   void* field, void* stream) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
+    if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
+    check_device(pl);
+    fmm::evaluate(pl, 1, q, nrhs, pot, field, (hipStream_t)stream);
+  });
+}
+
+fmm_status fmm_adjoint(fmm_plan* pl, const void* q, const void* g, int nrhs,
+                       const void* field_fwd, void* grad_q, void* grad_x, void* stream) {
+  return guard([&] {
+    if (!pl) throw Error{FMM_EINVAL, "plan is NULL"};
+    if (!g || !grad_q) throw Error{FMM_EINVAL, "g and grad_q must not be NULL"};
+    if (grad_x && (!q || !field_fwd))
+      throw Error{FMM_EINVAL, "grad_x needs q and field_fwd"};
+    if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
+    check_device(pl);
+    const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+    const hipStream_t st = (hipStream_t)stream;
+    for (int r = 0; r < nrhs; ++r) {
+      const size_t o1 = es * (size_t)pl->n * r, o3 = 3 * o1;
+      fmm::evaluate(pl, 1, (const char*)g + o1, 1, (char*)grad_q + o1,
+                    grad_x ? pl->field_t : nullptr, st);
+      if (grad_x)
+        fmm::adjoint_combine(pl, (const char*)q + o1, (const char*)g + o1,
+                             (const char*)field_fwd + o3, pl->field_t, (char*)grad_x + o3, st);
+    }
   });
 }
 
@@ -254,8 +293,9 @@ fmm_status fmm_plan_get_lists(const fmm_plan* pl, int64_t* m2l_src, int64_t* m2l
           if (tgt) tgt[k] = t;
         }
     };
-    fetch(pl->m2l_ptr, pl->m2l_src, pl->nbox, pl->n_m2l, m2l_src, m2l_tgt);
-    fetch(pl->p2p_ptr, pl->p2p_src, pl->nleaf, pl->n_p2p, p2p_src, p2p_tgt);
+    const ListSet& F = pl->lists[0];
+    fetch(F.m2l_ptr, F.m2l_src, pl->nbox, F.n_m2l, m2l_src, m2l_tgt);
+    fetch(F.p2p_ptr, F.p2p_src, pl->nleaf, F.n_p2p, p2p_src, p2p_tgt);
   });
 }
 

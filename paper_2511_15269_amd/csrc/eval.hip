@@ -1,7 +1,12 @@
 // FMM evaluation pass (stage order of Sec. III.A: sort, P2M, M2M, M2L, L2L,
 // L2P, P2P), hand-written HIP kernels for gfx950.
 //
-// Coefficients are kept normalised (tables.h), box-major: [box][(P+1)^2].
+// Coefficients are kept normalised (tables.h) and scaled per box by its
+// radius rho (multipole degree n divided by rho^n, local degree n multiplied
+// by rho^{n+1}), box-major: [box][(P+1)^2].  With this scaling every
+// translation below multiplies by ratios of lengths that are at most 1
+// (child/parent radius, centre offset/parent radius, radius/distance of an
+// admissible pair), so single precision cannot overflow.
 // All translations are rotation based (Sec. II.D, App. B): for a shift from
 // an old centre to a new one with b = old - new = r (sin B cos A,
 // sin B sin A, cos B), the coefficients are rotated so that b points along
@@ -123,19 +128,25 @@ __device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
 
 enum { kM2M = 0, kM2L = 1, kL2L = 2 };
 
-// z-axis operators of App. B.3 (normalised), in place
+// z-axis operators of App. B.3 in the normalised, radius-scaled basis, in
+// place.  With r the shift length:
+//   M2L (a = rho_src/r, b = rho_tgt/r):   out_n = b^{n+1} sum_k T_nk a^k v_k
+//   M2M (a = r/rho_par, b = rho_chi/rho_par): out_n = sum_{k<=n} T_nk a^{n-k} b^k v_k
+//   L2L (a = r/rho_par, b = rho_chi/rho_par): out_n = b^{n+1} sum_{k>=n} T_nk a^{k-n} v_k
 template <int P, int KIND, typename T>
-__device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
-  if (KIND == kM2L) {
-    const T ir = T(1) / r;
-    T ip[2 * P + 2];
-    ip[0] = T(1);
+__device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab) {
+  T pa[2 * P + 2], pb[P + 2];
+  pa[0] = T(1);
+  pb[0] = T(1);
 #pragma unroll
-    for (int j = 1; j <= 2 * P + 1; ++j) ip[j] = ip[j - 1] * ir;
+  for (int j = 1; j <= P; ++j) pa[j] = pa[j - 1] * a;
+#pragma unroll
+  for (int j = 1; j <= P + 1; ++j) pb[j] = pb[j - 1] * b;
+  if (KIND == kM2L) {
 #pragma unroll
     for (int n = 0; n <= P; ++n)
 #pragma unroll
-      for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= ip[n];
+      for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pa[n];
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
@@ -147,16 +158,18 @@ __device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
         T acc = T(0);
 #pragma unroll
         for (int k = am; k <= P; ++k) acc = fma(tb[c++], v[cidx(k, m)], acc);
-        o[n] = acc * ip[n + 1];
+        o[n] = acc * pb[n + 1];
       }
 #pragma unroll
       for (int n = am; n <= P; ++n) v[cidx(n, m)] = m < 0 ? -o[n] : o[n];
     }
   } else {
-    T pw[P + 1];
-    pw[0] = T(1);
+    if (KIND == kM2M) {
 #pragma unroll
-    for (int j = 1; j <= P; ++j) pw[j] = pw[j - 1] * r;
+      for (int n = 0; n <= P; ++n)
+#pragma unroll
+        for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pb[n];
+    }
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
@@ -168,10 +181,11 @@ __device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
         T acc = T(0);
         if (KIND == kM2M) {
 #pragma unroll
-          for (int k = am; k <= n; ++k) acc = fma(tb[c++] * pw[n - k], v[cidx(k, m)], acc);
+          for (int k = am; k <= n; ++k) acc = fma(tb[c++] * pa[n - k], v[cidx(k, m)], acc);
         } else {
 #pragma unroll
-          for (int k = n; k <= P; ++k) acc = fma(tb[c++] * pw[k - n], v[cidx(k, m)], acc);
+          for (int k = n; k <= P; ++k) acc = fma(tb[c++] * pa[k - n], v[cidx(k, m)], acc);
+          acc *= pb[n + 1];
         }
         o[n] = acc;
       }
@@ -182,11 +196,12 @@ __device__ __forceinline__ void zshift(T* v, T r, const T* __restrict__ tab) {
 }
 
 // Rotate so that b points along +z, shift along z, rotate back.
-// b = old centre - new centre.  M2L maps multipole (regular-basis sign
-// convention) to local (singular-basis convention); M2M keeps the former,
-// L2L the latter.
+// b = old centre - new centre; rho_old, rho_new the scale lengths of the
+// two boxes.  M2L maps multipole (regular-basis sign convention) to local
+// (singular-basis convention); M2M keeps the former, L2L the latter.
 template <int P, int KIND, typename T>
 __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double bz,
+                                             double rho_old, double rho_new,
                                              const T* __restrict__ tab) {
   const double rxy2 = bx * bx + by * by;
   const double rxy = sqrt(rxy2);
@@ -199,6 +214,17 @@ __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double 
   if (r > 0.0) {
     cb = bz / r;
     sb = rxy / r;
+  }
+  double a, b;
+  if (KIND == kM2L) {
+    a = rho_old / r;
+    b = rho_new / r;
+  } else if (KIND == kM2M) {
+    a = r / rho_new;
+    b = rho_old / rho_new;
+  } else {
+    a = r / rho_old;
+    b = rho_new / rho_old;
   }
   T am_c[P + 1], am_s[P + 1], bm_c[P + 1], bm_s[P + 1];
   powers<P, T>(T(ca), T(sa), am_c, am_s);
@@ -214,7 +240,7 @@ __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double 
   else
     azimuth<P, T, -1, 0>(v, bm_c, bm_s);
   apply_y<P, true, T>(v, tab);
-  zshift<P, KIND, T>(v, T(r), tab);
+  zshift<P, KIND, T>(v, T(a), T(b), tab);
   // back: Y, Rz(B), Y^T, Rz(A - pi/2)
   apply_y<P, false, T>(v, tab);
   if (KIND == kM2M)
@@ -228,10 +254,15 @@ __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double 
     azimuth<P, T, +1, 1>(v, am_c, am_s);
 }
 
-// Source point in leaf order with its charge, read by P2M and P2P (one
-// 32-byte record, so that a wave-uniform read is a single scalar load).
+// Source points in leaf order with their charges, one 32-byte record per
+// point (so that a wave-uniform read is a single scalar load).  Positions
+// stay FP64 in both forms: the FP32 form takes each pair difference in FP64
+// and rounds it, so clustered points keep their separation and exactly
+// coincident points give exactly zero.
+template <typename T>
 struct alignas(32) Src {
-  double x, y, z, q;
+  double x, y, z;
+  T q;
 };
 
 // ---------------------------------------------------------------- P2M
@@ -276,11 +307,14 @@ __device__ __forceinline__ void regular_basis(T x, T y, T z, F&& f) {
   }
 }
 
+// C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole)
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(
-    int nleaf, int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
-    const Src* __restrict__ src, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
+    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const double* __restrict__ xs, const double* __restrict__ ys,
+    const double* __restrict__ zs, const Src<T>* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
     const T* __restrict__ tab, T* __restrict__ C) {
   constexpr int K = K_<P>::value;
   __shared__ T red[K][65];
@@ -291,11 +325,10 @@ __global__ __launch_bounds__(64) void k_p2m(
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
-  const double ox = cx[g], oy = cy[g], oz = cz[g];
+  const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   for (int j = st + lane; j < en; j += 64) {
-    const Src a = src[j];
-    const T qj = T(a.q);
-    regular_basis<P, T>(T(a.x - ox), T(a.y - oy), T(a.z - oz),
+    const T qj = src[j].q;
+    regular_basis<P, T>(T((xs[j] - ox) * ir), T((ys[j] - oy) * ir), T((zs[j] - oz) * ir),
                         [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
   }
 #pragma unroll
@@ -313,7 +346,8 @@ template <int P, typename T>
 __global__ __launch_bounds__(64) void k_m2m(
     int64_t nchild, int64_t child0, int64_t parent0, int s,
     const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const T* __restrict__ tab, T* C) {
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ tab, T* C) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < nchild;
@@ -322,7 +356,8 @@ __global__ __launch_bounds__(64) void k_m2m(
   T v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = live ? C[c * K + k] : T(0);
-  rotate_shift<P, kM2M, T>(v, cx[c] - cx[pa], cy[c] - cy[pa], cz[c] - cz[pa], tab);
+  rotate_shift<P, kM2M, T>(v, cx[c] - cx[pa], cy[c] - cy[pa], cz[c] - cz[pa], scale[c],
+                           scale[pa], tab);
   const int nch = 1 << s;
   for (int off = 1; off < nch; off <<= 1) {
 #pragma unroll
@@ -341,13 +376,14 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
     const int32_t* __restrict__ item_begin, const int32_t* __restrict__ item_end,
     const int32_t* __restrict__ src, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ cz,
-    const T* __restrict__ C, const T* __restrict__ tab, T* __restrict__ partial) {
+    const double* __restrict__ scale, const T* __restrict__ C,
+    const T* __restrict__ tab, T* __restrict__ partial) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const int t = item_tgt[i];
   const int jb = item_begin[i], je = item_end[i];
-  const double tx = cx[t], ty = cy[t], tz = cz[t];
+  const double tx = cx[t], ty = cy[t], tz = cz[t], rt = scale[t];
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
@@ -356,7 +392,8 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
     T v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = C[(int64_t)sidx * K + k];
-    rotate_shift<P, kM2L, T>(v, cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, tab);
+    rotate_shift<P, kM2L, T>(v, cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, scale[sidx], rt,
+                             tab);
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += v[k];
   }
@@ -371,7 +408,8 @@ __global__ __launch_bounds__(64) void k_l2l(
     int64_t nb, int64_t box0, int64_t parent0, int s,
     const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
     const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const T* __restrict__ tab, T* D) {
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ tab, T* D) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
@@ -388,7 +426,8 @@ __global__ __launch_bounds__(64) void k_l2l(
     T v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
-    rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], tab);
+    rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
+                             scale[t], tab);
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += v[k];
   }
@@ -396,7 +435,7 @@ __global__ __launch_bounds__(64) void k_l2l(
   for (int k = 0; k < K; ++k) D[t * K + k] = acc[k];
 }
 
-// ---------------------------------------------------------------- L2P+P2P
+// ---------------------------------------------------------------- L2P
 // Regular basis and its gradient (App. A.1, A.3; the sectoral gradient
 // without the printed leading minus), accumulated against w[k] = weight *
 // local coefficient: pot += w R, grad += w grad R.
@@ -480,22 +519,18 @@ __device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ 
   }
 }
 
-__device__ __forceinline__ double inv_sqrt(double r2) {
-  // hardware estimate refined by one Newton step
-  const double y = __builtin_amdgcn_rsq(r2);
-  return y * fma(-0.5 * r2, y * y, 1.5);
-}
-__device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
-
-// L2P: u = -1/(4 pi) sum w_m D R-hat, field = -grad u, at every point of the
+// L2P: u = -1/(4 pi) (1/rho) sum w_m D R-hat(y), y = (x - c)/rho, and
+// field = -grad u (an extra 1/rho from the chain rule), at every point of the
 // target leaf; writes (not adds) the outputs in input order.
 template <int P, typename T, bool FIELD>
 __global__ __launch_bounds__(64) void k_l2p(
     int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
-    const int32_t* __restrict__ perm, const Src* __restrict__ src,
+    const int32_t* __restrict__ perm, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
     const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const T* __restrict__ D,
-    const T* __restrict__ tab, T* __restrict__ pot, T* __restrict__ field) {
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ D, const T* __restrict__ tab, T* __restrict__ pot,
+    T* __restrict__ field) {
   constexpr int K = K_<P>::value;
   __shared__ T w[K];
   const int leaf = blockIdx.x;
@@ -504,35 +539,49 @@ __global__ __launch_bounds__(64) void k_l2p(
   for (int k = lane; k < K; k += 64) w[k] = D[g * K + k] * tab[tab_l2p(P) + k];
   __syncthreads();
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
-  const double ox = cx[g], oy = cy[g], oz = cz[g];
+  const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
+  const T fu = T(-kInv4Pi * ir), ff = T(kInv4Pi * ir * ir);
   for (int i = st + lane; i < en; i += 64) {
-    const Src a = src[i];
     T fp = T(0), fx = T(0), fy = T(0), fz = T(0);
-    local_eval<P, T>(T(a.x - ox), T(a.y - oy), T(a.z - oz), w, fp, fx, fy, fz);
+    local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w, fp,
+                     fx, fy, fz);
     const int o = perm[i];
-    pot[o] = -T(kInv4Pi) * fp;
+    pot[o] = fu * fp;
     if (FIELD) {
-      field[3 * (int64_t)o + 0] = T(kInv4Pi) * fx;
-      field[3 * (int64_t)o + 1] = T(kInv4Pi) * fy;
-      field[3 * (int64_t)o + 2] = T(kInv4Pi) * fz;
+      field[3 * (int64_t)o + 0] = ff * fx;
+      field[3 * (int64_t)o + 1] = ff * fy;
+      field[3 * (int64_t)o + 2] = ff * fz;
     }
   }
 }
 
-// P2P: adds -1/(4 pi) sum q/r and the matching field over the direct list.
-// Block = target leaf, lane = target point; all lanes walk the same source
-// points, so each source record is one wave-uniform (scalar) load, fetched
-// in chunks of kChunk.
-constexpr int kChunk = 8;
+// ---------------------------------------------------------------- P2P
+__device__ __forceinline__ double inv_sqrt(double r2) {
+  // hardware estimate refined by one Newton step
+  const double y = __builtin_amdgcn_rsq(r2);
+  return y * fma(-0.5 * r2, y * y, 1.5);
+}
+__device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+// Neumaier's compensated addition: s + c carries the running sum.
+template <typename T>
+__device__ __forceinline__ void neumaier(T& s, T& c, T x) {
+  const T t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+// One source point against the lane's target at (xi, yi, zi): the
+// difference is taken in FP64 and rounded to T; pairs at distance 0
+// contribute nothing.
 template <typename T, bool FIELD>
-__device__ __forceinline__ void p2p_pair(const Src& s, double xi, double yi, double zi,
+__device__ __forceinline__ void p2p_pair(const Src<T>& s, double xi, double yi, double zi,
                                          T& u, T& gx, T& gy, T& gz) {
   const T dx = T(xi - s.x), dy = T(yi - s.y), dz = T(zi - s.z);
   const T r2 = dx * dx + dy * dy + dz * dz;
   const T inv0 = inv_sqrt(r2);
-  const T inv = r2 > T(0) ? inv0 : T(0);  // distance 0 contributes nothing
-  const T qi = T(s.q) * inv;
+  const T inv = r2 > T(0) ? inv0 : T(0);
+  const T qi = s.q * inv;
   u += qi;
   if (FIELD) {
     const T q3 = qi * inv * inv;
@@ -542,45 +591,72 @@ __device__ __forceinline__ void p2p_pair(const Src& s, double xi, double yi, dou
   }
 }
 
-// G source groups: lanes [g*64/G, (g+1)*64/G) share targets with the
-// other groups but walk every G-th source point starting at point g.  G = 1
-// keeps all source reads wave-uniform (scalar loads); G = 2, 4 fill the
-// wave when leaves hold at most 32 or 16 points.  Group sums are combined
-// with cross-lane shuffles in a fixed order.
+constexpr int kChunk = 8;
+
+// P2P: adds -1/(4 pi) sum q/r and the matching field over the direct list.
+// Block = target leaf, lane = target point.  G source groups: lanes
+// [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
+// G-th source point starting at point g.  G = 1 keeps all source reads
+// wave-uniform (scalar loads); G = 2, 4 fill the wave when leaves hold at
+// most 32 or 16 points.  Per source leaf the partial sums are added to the
+// running sums with Neumaier compensation (FP32 form); group sums are then
+// combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
-    const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
-    const Src* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
-    const int32_t* __restrict__ p2p_src, T* __restrict__ pot,
-    T* __restrict__ field) {
+    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ perm, const Src<T>* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const int32_t* __restrict__ p2p_ptr, const int32_t* __restrict__ p2p_src,
+    T* __restrict__ pot, T* __restrict__ field) {
   constexpr int TL = 64 / G;  // targets per pass
+  constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  const int g = lane / TL;
+  const int g = G == 1 ? 0 : lane / TL;
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
   for (int i0 = st; i0 < en; i0 += TL) {
     const int i = i0 + lane % TL;
     const bool live = i < en;
-    const Src a = src[live ? i : st];
+    const Src<T> a = src[live ? i : st];
     T u = T(0), gx = T(0), gy = T(0), gz = T(0);
+    T cu = T(0), cgx = T(0), cgy = T(0), cgz = T(0);
     for (int k = pb; k < pe; ++k) {
       const int sl = p2p_src[k];
       const int js = leaf_start[sl], cnt = leaf_start[sl + 1] - js;
+      T lu = T(0), lx = T(0), ly = T(0), lz = T(0);
       const int full = cnt / G;  // points per group present in every group
-      const Src* base = src + js + g;
+      const Src<T>* base = src + js + g;
       int c = 0;
       for (; c + kChunk <= full; c += kChunk) {
-        Src r[kChunk];
+        Src<T> r[kChunk];
 #pragma unroll
         for (int t = 0; t < kChunk; ++t) r[t] = base[(c + t) * G];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, u, gx, gy, gz);
+        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, lu, lx, ly, lz);
       }
-      for (; c < full; ++c) p2p_pair<T, FIELD>(base[c * G], a.x, a.y, a.z, u, gx, gy, gz);
+      for (; c < full; ++c) p2p_pair<T, FIELD>(base[c * G], a.x, a.y, a.z, lu, lx, ly, lz);
       if (G > 1 && g < cnt - full * G)
-        p2p_pair<T, FIELD>(base[full * G], a.x, a.y, a.z, u, gx, gy, gz);
+        p2p_pair<T, FIELD>(base[full * G], a.x, a.y, a.z, lu, lx, ly, lz);
+      if (kComp) {
+        neumaier(u, cu, lu);
+        if (FIELD) {
+          neumaier(gx, cgx, lx);
+          neumaier(gy, cgy, ly);
+          neumaier(gz, cgz, lz);
+        }
+      } else {
+        u += lu;
+        gx += lx;
+        gy += ly;
+        gz += lz;
+      }
     }
+    u += cu;
+    gx += cgx;
+    gy += cgy;
+    gz += cgz;
 #pragma unroll
     for (int off = TL; off < 64; off <<= 1) {
       u += __shfl_xor(u, off, 64);
@@ -603,24 +679,36 @@ __global__ __launch_bounds__(64) void k_p2p(
   }
 }
 
-// sort stage: sources in leaf order with their charges
+// sort stage: source records in leaf order with their charges
 template <typename T>
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm,
                          const double* __restrict__ xs, const double* __restrict__ ys,
                          const double* __restrict__ zs, const T* __restrict__ q,
-                         Src* __restrict__ src) {
+                         Src<T>* __restrict__ src) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) src[j] = Src{xs[j], ys[j], zs[j], double(q[perm[j]])};
+  if (j < n) src[j] = Src<T>{xs[j], ys[j], zs[j], q[perm[j]]};
+}
+
+// d/dx_k of sum_i g_i u_i: g_k grad u(x_k) (x_k as a target of the forward
+// pass) + q_k grad v(x_k) (x_k as a source, v = transposed pass with charges
+// g); fields are -grad.
+template <typename T>
+__global__ void k_adjoint_combine(int64_t n, const T* __restrict__ q, const T* __restrict__ g,
+                                  const T* __restrict__ ff, const T* __restrict__ ft,
+                                  T* __restrict__ gx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int64_t i = e / 3;
+  gx[e] = -(g[i] * ff[e] + q[i] * ft[e]);
 }
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int P, typename T>
-void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
-  constexpr int K = K_<P>::value;
+void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStream_t st) {
   const int L = pl->L, s = pl->s;
   const T* tab = (const T*)pl->tables;
-  Src* src = (Src*)pl->src;
+  Src<T>* src = (Src<T>*)pl->src;
   T* C = (T*)pl->C;
   T* D = (T*)pl->D;
   T* part = (T*)pl->partial;
@@ -638,39 +726,42 @@ void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
   mark(0);
   k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
   mark(1);
-  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>((int)pl->nleaf, leaf0, pl->leaf_start,
-                                                  src, pl->cx, pl->cy, pl->cz, tab, C);
+  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs,
+                                                  src, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
   mark(2);
   for (int l = L - 1; l >= 0; --l) {
     const int64_t nchild = pl->level_off[l + 2] - pl->level_off[l + 1];
-    k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(
-        nchild, pl->level_off[l + 1], pl->level_off[l], s, pl->cx, pl->cy,
-        pl->cz, tab, C);
+    k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, pl->level_off[l + 1], pl->level_off[l],
+                                                   s, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
   }
   mark(3);
-  if (pl->n_items > 0)
-    k_m2l<P, T><<<blocks(pl->n_items, kM2LThreads), kM2LThreads, 0, st>>>(
-        pl->n_items, pl->item_tgt, pl->item_begin, pl->item_end, pl->m2l_src,
-        pl->cx, pl->cy, pl->cz, C, tab, part);
+  if (Ls.n_items > 0)
+    k_m2l<P, T><<<blocks(Ls.n_items, kM2LThreads), kM2LThreads, 0, st>>>(
+        Ls.n_items, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
+        pl->cz, pl->scale, C, tab, part);
   mark(4);
   for (int l = 0; l <= L; ++l) {
     const int64_t nb = pl->level_off[l + 1] - pl->level_off[l];
-    k_l2l<P, T><<<blocks(nb, 64), 64, 0, st>>>(
-        nb, pl->level_off[l], l > 0 ? pl->level_off[l - 1] : -1, s,
-        pl->item_ptr, part, pl->cx, pl->cy, pl->cz, tab, D);
+    k_l2l<P, T><<<blocks(nb, 64), 64, 0, st>>>(nb, pl->level_off[l],
+                                               l > 0 ? pl->level_off[l - 1] : -1, s,
+                                               Ls.item_ptr, part, pl->cx, pl->cy, pl->cz,
+                                               pl->scale, tab, D);
   }
   mark(5);
   if (field)
     k_l2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, src, pl->cx, pl->cy, pl->cz, D, tab, pot, field);
+        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
+        pl->scale, D, tab, pot, field);
   else
     k_l2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, src, pl->cx, pl->cy, pl->cz, D, tab, pot, field);
+        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
+        pl->scale, D, tab, pot, field);
   mark(6);
   const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
   auto p2p = [&](auto kern) {
-    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, pl->p2p_ptr,
-                                              pl->p2p_src, pot, field);
+    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->perm, src, pl->cx,
+                                              pl->cy, pl->cz, pl->scale, Ls.p2p_ptr,
+                                              Ls.p2p_src, pot, field);
   };
   if (field) {
     if (G == 1) p2p(k_p2p<T, true, 1>);
@@ -683,15 +774,15 @@ void run(fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
   }
   mark(7);
   FMM_HIP(hipGetLastError());
-  (void)K;
 }
 
 template <typename T>
-void dispatch(int p, fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st) {
+void dispatch(int p, fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field,
+              hipStream_t st) {
   switch (p) {
 #define FMM_CASE(PP) \
   case PP:           \
-    run<PP, T>(pl, q, pot, field, st); \
+    run<PP, T>(pl, Ls, q, pot, field, st); \
     break;
     FMM_CASE(1) FMM_CASE(2) FMM_CASE(3) FMM_CASE(4) FMM_CASE(5)
     FMM_CASE(6) FMM_CASE(7) FMM_CASE(8) FMM_CASE(9) FMM_CASE(10)
@@ -703,18 +794,33 @@ void dispatch(int p, fmm_plan* pl, const T* q, T* pot, T* field, hipStream_t st)
 
 }  // namespace
 
-void evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot, void* field,
+void evaluate(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
               hipStream_t st) {
   const int64_t n = pl->n;
+  const ListSet& Ls = pl->lists[dir];
   for (int r = 0; r < nrhs; ++r) {
     if (pl->prm.precision == FMM_FP32) {
-      dispatch<float>(pl->prm.p, pl, (const float*)q + r * n, (float*)pot + r * n,
+      dispatch<float>(pl->prm.p, pl, Ls, (const float*)q + r * n, (float*)pot + r * n,
                       field ? (float*)field + 3 * r * n : nullptr, st);
     } else {
-      dispatch<double>(pl->prm.p, pl, (const double*)q + r * n, (double*)pot + r * n,
+      dispatch<double>(pl->prm.p, pl, Ls, (const double*)q + r * n, (double*)pot + r * n,
                        field ? (double*)field + 3 * r * n : nullptr, st);
     }
   }
+}
+
+void adjoint_combine(fmm_plan* pl, const void* q, const void* g, const void* field_fwd,
+                     const void* field_t, void* grad_x, hipStream_t st) {
+  const int64_t n = pl->n;
+  if (pl->prm.precision == FMM_FP32)
+    k_adjoint_combine<float><<<blocks(3 * n, 256), 256, 0, st>>>(
+        n, (const float*)q, (const float*)g, (const float*)field_fwd, (const float*)field_t,
+        (float*)grad_x);
+  else
+    k_adjoint_combine<double><<<blocks(3 * n, 256), 256, 0, st>>>(
+        n, (const double*)q, (const double*)g, (const double*)field_fwd,
+        (const double*)field_t, (double*)grad_x);
+  FMM_HIP(hipGetLastError());
 }
 
 }  // namespace fmm

@@ -45,6 +45,22 @@ struct Tables {
   void* dev32 = nullptr;     // device copy (float)
 };
 
+// Interaction lists of one direction, CSR by target.  M2L work items: item
+// i covers pairs [item_begin[i], item_end[i]) of target item_tgt[i]; the
+// items of one target are consecutive and item_ptr[t]..item_ptr[t+1] lists
+// them.
+struct ListSet {
+  int32_t* m2l_ptr = nullptr;  // [nbox+1]
+  int32_t* m2l_src = nullptr;  // [n_m2l]
+  int32_t* p2p_ptr = nullptr;  // [nleaf+1]
+  int32_t* p2p_src = nullptr;  // [n_p2p]
+  int32_t* item_tgt = nullptr;
+  int32_t* item_begin = nullptr;
+  int32_t* item_end = nullptr;
+  int32_t* item_ptr = nullptr;  // [nbox+1]
+  int64_t n_m2l = 0, n_p2p = 0, n_items = 0;
+};
+
 }  // namespace fmm
 
 struct fmm_plan {
@@ -65,28 +81,21 @@ struct fmm_plan {
   double* cy = nullptr;
   double* cz = nullptr;
   double* radius = nullptr;  // [nbox]
+  double* scale = nullptr;   // [nbox] length scale of the box's expansions
+  int32_t* leaf_of = nullptr;  // [n] leaf of each leaf-ordered point
   int32_t max_leaf_count = 0;
 
-  // lists (device), CSR by target
-  int32_t* m2l_ptr = nullptr;  // [nbox+1]
-  int32_t* m2l_src = nullptr;  // [n_m2l]
-  int32_t* p2p_ptr = nullptr;  // [nleaf+1]
-  int32_t* p2p_src = nullptr;  // [n_p2p]
-  // M2L work items: item i covers pairs [item_begin[i], item_end[i]) of
-  // target item_tgt[i]; items of one target are consecutive and
-  // item_ptr[t]..item_ptr[t+1] lists them.
-  int32_t* item_tgt = nullptr;
-  int32_t* item_begin = nullptr;
-  int32_t* item_end = nullptr;
-  int32_t* item_ptr = nullptr;  // [nbox+1]
-  int64_t n_items = 0;
-  int64_t n_m2l = 0, n_p2p = 0, p2p_inter = 0;
+  // lists (device): [0] forward, [1] transposed (every pair reversed; the
+  // adjoint operator)
+  fmm::ListSet lists[2];
+  int64_t p2p_inter = 0;
 
   // evaluation workspace
   void* src = nullptr;       // [n] {x, y, z, q} in leaf order
   void* C = nullptr;         // [nbox][K]   multipoles (normalised)
   void* D = nullptr;         // [nbox][K]   locals (normalised)
-  void* partial = nullptr;   // [n_items][K] M2L partial sums
+  void* partial = nullptr;   // [max n_items][K] M2L partial sums
+  void* field_t = nullptr;   // [n][3] field of the transposed pass (adjoint)
   const void* tables = nullptr;  // device operator tables for (p, precision)
 
   std::vector<fmm::DevBuf> bufs;
@@ -109,9 +118,12 @@ void build_tree(fmm_plan* pl, const double* pos, hipStream_t st);
 void build_lists(fmm_plan* pl, hipStream_t st);
 // Operator tables for order p (tables.cpp), cached per process/device.
 const void* get_tables(int p, int precision, int device);
-// Evaluation (eval.hip).
-void evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot, void* field,
+// Evaluation (eval.hip): dir 0 = G-hat, dir 1 = G-hat^T.
+void evaluate(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
               hipStream_t st);
+// Adjoint combine: grad_x = -(g * field_fwd + q * field_t) (eval.hip).
+void adjoint_combine(fmm_plan* pl, const void* q, const void* g, const void* field_fwd,
+                     const void* field_t, void* grad_x, hipStream_t st);
 
 // Direct summation (direct.hip).
 void direct_sum(int64_t n, const double* pos, const void* q, int precision,

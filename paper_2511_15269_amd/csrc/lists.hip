@@ -119,6 +119,16 @@ struct Scratch {
   }
 };
 
+// (source << 32 | target) keys of a CSR list: the reversed pairs.
+__global__ void k_transposed_keys(int64_t ntgt, const int32_t* __restrict__ ptr,
+                                  const int32_t* __restrict__ src,
+                                  uint64_t* __restrict__ keys) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  for (int32_t k = ptr[t]; k < ptr[t + 1]; ++k)
+    keys[k] = ((uint64_t)src[k] << 32) | (uint64_t)t;
+}
+
 int bits_for(int64_t v) {
   int b = 1;
   while (b < 63 && ((int64_t)1 << b) <= v) ++b;
@@ -141,6 +151,43 @@ void keys_to_csr(fmm_plan* pl, Scratch& sc, uint64_t* keys, int64_t nk,
   FMM_HIP(hipGetLastError());
 }
 
+// M2L work items of a list set: at most kItemPairs pairs each, consecutive
+// per target.
+void make_items(fmm_plan* pl, ListSet& S, hipStream_t st) {
+  const int kItemPairs = 16;
+  std::vector<int32_t> mptr(pl->nbox + 1);
+  FMM_HIP(hipMemcpyAsync(mptr.data(), S.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
+                         hipMemcpyDeviceToHost, st));
+  FMM_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> it_t, it_b, it_e, it_ptr(pl->nbox + 1);
+  for (int64_t t = 0; t < pl->nbox; ++t) {
+    it_ptr[t] = (int32_t)it_t.size();
+    for (int32_t b = mptr[t]; b < mptr[t + 1]; b += kItemPairs) {
+      it_t.push_back((int32_t)t);
+      it_b.push_back(b);
+      it_e.push_back(std::min(b + kItemPairs, mptr[t + 1]));
+    }
+  }
+  it_ptr[pl->nbox] = (int32_t)it_t.size();
+  S.n_items = (int64_t)it_t.size();
+  const size_t ni = std::max<size_t>(it_t.size(), 1);
+  S.item_tgt = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
+  S.item_begin = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
+  S.item_end = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
+  S.item_ptr = (int32_t*)plan_alloc(pl, sizeof(int32_t) * (pl->nbox + 1));
+  if (!it_t.empty()) {
+    FMM_HIP(hipMemcpyAsync(S.item_tgt, it_t.data(), sizeof(int32_t) * it_t.size(),
+                           hipMemcpyHostToDevice, st));
+    FMM_HIP(hipMemcpyAsync(S.item_begin, it_b.data(), sizeof(int32_t) * it_b.size(),
+                           hipMemcpyHostToDevice, st));
+    FMM_HIP(hipMemcpyAsync(S.item_end, it_e.data(), sizeof(int32_t) * it_e.size(),
+                           hipMemcpyHostToDevice, st));
+  }
+  FMM_HIP(hipMemcpyAsync(S.item_ptr, it_ptr.data(), sizeof(int32_t) * it_ptr.size(),
+                         hipMemcpyHostToDevice, st));
+  FMM_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace
 
 void build_lists(fmm_plan* pl, hipStream_t st) {
@@ -152,6 +199,16 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
   FMM_HIP(hipMemcpyAsync(rad.data(), pl->radius, sizeof(double) * pl->nbox,
                          hipMemcpyDeviceToHost, st));
   FMM_HIP(hipStreamSynchronize(st));
+  // Length scale of each box's expansions: its radius, floored at 2^-30 of
+  // the root radius (boxes whose points coincide have radius 0).
+  {
+    const double floor_r = rad[0] > 0.0 ? std::ldexp(rad[0], -30) : 1.0;
+    std::vector<double> scl(pl->nbox);
+    for (int64_t b = 0; b < pl->nbox; ++b) scl[b] = std::max(rad[b], floor_r);
+    FMM_HIP(hipMemcpyAsync(pl->scale, scl.data(), sizeof(double) * pl->nbox,
+                           hipMemcpyHostToDevice, st));
+    FMM_HIP(hipStreamSynchronize(st));
+  }
   std::vector<double> avg(L + 1);
   for (int l = 0; l <= L; ++l) {
     double acc = 0.0;
@@ -217,8 +274,10 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
                            hipMemcpyDeviceToDevice, st));
     o += pr.second;
   }
-  keys_to_csr(pl, sc, all, n_m2l, pl->nbox, &pl->m2l_src, &pl->m2l_ptr, st);
-  pl->n_m2l = n_m2l;
+  ListSet& F = pl->lists[0];
+  ListSet& A = pl->lists[1];
+  keys_to_csr(pl, sc, all, n_m2l, pl->nbox, &F.m2l_src, &F.m2l_ptr, st);
+  F.n_m2l = A.n_m2l = n_m2l;
   // P2P CSR over leaves (what is left once both sides reached the leaves)
   if (!(ls == L && lt == L)) np = 0;
   uint64_t* pk = (uint64_t*)sc.get(sizeof(uint64_t) * std::max<int64_t>(np, 1));
@@ -226,17 +285,22 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
     k_keys_from_pairs<<<blocks(np, T), T, 0, st>>>(np, ps, pt, pk);
     FMM_HIP(hipGetLastError());
   }
-  keys_to_csr(pl, sc, pk, np, pl->nleaf, &pl->p2p_src, &pl->p2p_ptr, st);
-  pl->n_p2p = np;
+  keys_to_csr(pl, sc, pk, np, pl->nleaf, &F.p2p_src, &F.p2p_ptr, st);
+  F.n_p2p = A.n_p2p = np;
+  // transposed lists: every (source, target) pair reversed
+  uint64_t* tk = (uint64_t*)sc.get(sizeof(uint64_t) * std::max<int64_t>(std::max(n_m2l, np), 1));
+  k_transposed_keys<<<blocks(pl->nbox, T), T, 0, st>>>(pl->nbox, F.m2l_ptr, F.m2l_src, tk);
+  keys_to_csr(pl, sc, tk, n_m2l, pl->nbox, &A.m2l_src, &A.m2l_ptr, st);
+  k_transposed_keys<<<blocks(pl->nleaf, T), T, 0, st>>>(pl->nleaf, F.p2p_ptr, F.p2p_src, tk);
+  keys_to_csr(pl, sc, tk, np, pl->nleaf, &A.p2p_src, &A.p2p_ptr, st);
+  FMM_HIP(hipGetLastError());
 
-  // host copies for work items and counts
-  std::vector<int32_t> mptr(pl->nbox + 1), pptr(pl->nleaf + 1), psrc(std::max<int64_t>(np, 1)),
+  // P2P interaction count (same in both directions)
+  std::vector<int32_t> pptr(pl->nleaf + 1), psrc(std::max<int64_t>(np, 1)),
       lstart(pl->nleaf + 1);
-  FMM_HIP(hipMemcpyAsync(mptr.data(), pl->m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
+  FMM_HIP(hipMemcpyAsync(pptr.data(), F.p2p_ptr, sizeof(int32_t) * (pl->nleaf + 1),
                          hipMemcpyDeviceToHost, st));
-  FMM_HIP(hipMemcpyAsync(pptr.data(), pl->p2p_ptr, sizeof(int32_t) * (pl->nleaf + 1),
-                         hipMemcpyDeviceToHost, st));
-  FMM_HIP(hipMemcpyAsync(psrc.data(), pl->p2p_src, sizeof(int32_t) * psrc.size(),
+  FMM_HIP(hipMemcpyAsync(psrc.data(), F.p2p_src, sizeof(int32_t) * psrc.size(),
                          hipMemcpyDeviceToHost, st));
   FMM_HIP(hipMemcpyAsync(lstart.data(), pl->leaf_start, sizeof(int32_t) * (pl->nleaf + 1),
                          hipMemcpyDeviceToHost, st));
@@ -246,36 +310,8 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
     for (int32_t k = pptr[t]; k < pptr[t + 1]; ++k)
       inter += (int64_t)(lstart[t + 1] - lstart[t]) * (lstart[psrc[k] + 1] - lstart[psrc[k]]);
   pl->p2p_inter = inter;
-
-  // M2L work items: at most kItemPairs pairs each, consecutive per target
-  const int kItemPairs = 16;
-  std::vector<int32_t> it_t, it_b, it_e, it_ptr(pl->nbox + 1);
-  for (int64_t t = 0; t < pl->nbox; ++t) {
-    it_ptr[t] = (int32_t)it_t.size();
-    for (int32_t b = mptr[t]; b < mptr[t + 1]; b += kItemPairs) {
-      it_t.push_back((int32_t)t);
-      it_b.push_back(b);
-      it_e.push_back(std::min(b + kItemPairs, mptr[t + 1]));
-    }
-  }
-  it_ptr[pl->nbox] = (int32_t)it_t.size();
-  pl->n_items = (int64_t)it_t.size();
-  const size_t ni = std::max<size_t>(it_t.size(), 1);
-  pl->item_tgt = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  pl->item_begin = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  pl->item_end = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  pl->item_ptr = (int32_t*)plan_alloc(pl, sizeof(int32_t) * (pl->nbox + 1));
-  if (!it_t.empty()) {
-    FMM_HIP(hipMemcpyAsync(pl->item_tgt, it_t.data(), sizeof(int32_t) * it_t.size(),
-                           hipMemcpyHostToDevice, st));
-    FMM_HIP(hipMemcpyAsync(pl->item_begin, it_b.data(), sizeof(int32_t) * it_b.size(),
-                           hipMemcpyHostToDevice, st));
-    FMM_HIP(hipMemcpyAsync(pl->item_end, it_e.data(), sizeof(int32_t) * it_e.size(),
-                           hipMemcpyHostToDevice, st));
-  }
-  FMM_HIP(hipMemcpyAsync(pl->item_ptr, it_ptr.data(), sizeof(int32_t) * it_ptr.size(),
-                         hipMemcpyHostToDevice, st));
-  FMM_HIP(hipStreamSynchronize(st));
+  make_items(pl, F, st);
+  make_items(pl, A, st);
 }
 
 }  // namespace fmm

@@ -190,3 +190,109 @@ def test_stage_profile_counts_passes(fmm):
     _, passes = plan.read_profile()
     assert passes == 0
     plan.set_profiling(False)
+
+
+FP32_CASES = [
+    # kind, n, p, leaf, s, theta
+    ("cube", 4096, 6, 64, 2, 0.6),
+    ("cube", 20000, 8, 64, 2, 0.7),
+    ("cube", 30000, 8, 128, 3, 0.7),
+    ("cluster", 30000, 10, 128, 2, 0.6),   # clustered, sigma = 0.01: scaled expansions
+    ("plummer", 20000, 8, 128, 2, 0.6),
+    ("lattice", 3000, 6, 16, 2, 0.6),      # coincident points in different leaves
+    ("cube", 100, 8, 128, 2, 0.6),
+]
+
+
+@pytest.mark.parametrize("kind,n,p,leaf,s,theta", FP32_CASES)
+def test_fp32_matches_oracle_fmm(fmm, kind, n, p, leaf, s, theta):
+    """FP32 form: within 1e-5 relative L2 of the FP64 oracle FMM (same tree,
+    lists and order) for potential and field."""
+    from oracle.fmm import fmm as oracle_fmm
+    _say(f"[fp32 vs oracle] {kind} n={n} p={p} leaf={leaf} s={s} theta={theta}")
+    pos, q = _inputs(kind, n, 8)
+    u0, f0 = oracle_fmm(pos, q, p, leaf, s, theta)
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=p, leaf_max=leaf, splits=s, theta=theta,
+                    precision="fp32")
+    u, f = plan.evaluate(torch.from_numpy(q).cuda().float())
+    u, f = u.double().cpu().numpy(), f.double().cpu().numpy()
+    eu, ef = _rel(u, u0), _rel(f, f0)
+    _say(f"    rel-L2 pot {eu:.2e} field {ef:.2e}")
+    assert eu <= 1e-5 and ef <= 1e-5
+
+
+ADJ_CASES = [
+    # kind, n, p, leaf, s, theta
+    ("cube", 4096, 6, 64, 2, 0.6),
+    ("plummer", 9000, 8, 128, 2, 0.6),
+    ("cube", 5000, 5, 40, 3, 0.7),
+    ("cluster", 8000, 7, 32, 1, 0.5),
+]
+
+
+@pytest.mark.parametrize("kind,n,p,leaf,s,theta", ADJ_CASES)
+def test_transposed_pass_matches_oracle_and_is_the_adjoint(fmm, kind, n, p, leaf, s, theta):
+    from oracle.fmm import fmm as oracle_fmm
+    from oracle.gradient import transpose_lists
+    from oracle.lists import build_lists
+    from oracle.tree import build_tree
+    _say(f"[transposed] {kind} n={n} p={p} leaf={leaf} s={s} theta={theta}")
+    pos, q = _inputs(kind, n, 9)
+    g = np.random.default_rng(10).uniform(-1, 1, n)
+    tr = build_tree(pos, leaf, s)
+    lt = transpose_lists(build_lists(tr, theta))
+    v0, fv0 = oracle_fmm(pos, g, p, leaf, s, theta, tree=tr, lists=lt)
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=p, leaf_max=leaf, splits=s, theta=theta)
+    qt, gt = torch.from_numpy(q).cuda(), torch.from_numpy(g).cuda()
+    v, fv = plan.evaluate_transposed(gt)
+    assert _rel(v.cpu().numpy(), v0) <= 1e-10
+    assert _rel(fv.cpu().numpy(), fv0) <= 1e-10
+    u, _ = plan.evaluate(qt, field=False)
+    lhs = float(torch.dot(gt, u))
+    rhs = float(torch.dot(v, qt))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_energy_gradient_matches_oracle(fmm, prec, tol):
+    from oracle.gradient import energy_gradient_fmm
+    from oracle.lists import build_lists
+    from oracle.tree import build_tree
+    n, p, leaf, s, theta = 6000, 8, 64, 2, 0.6
+    _say(f"[energy gradient] plummer n={n} {prec}")
+    pos, q = workloads.plummer(n, 18)
+    tr = build_tree(pos, leaf, s)
+    li = build_lists(tr, theta)
+    dq0, dx0 = energy_gradient_fmm(pos, q, p, leaf, s, theta, tr, li)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pos_t = torch.from_numpy(pos).cuda().requires_grad_(True)
+    q_t = torch.from_numpy(q).cuda().to(dt).requires_grad_(True)
+    plan = fmm.Plan(pos_t.detach(), p=p, leaf_max=leaf, splits=s, theta=theta, precision=prec)
+    E = fmm.fmm_energy(plan, q_t, pos_t)
+    gq, gx = torch.autograd.grad(E, (q_t, pos_t))
+    eq = _rel(gq.double().cpu().numpy(), dq0)
+    ex = _rel(gx.double().cpu().numpy(), dx0)
+    _say(f"    rel-L2 dE/dq {eq:.2e} dE/dx {ex:.2e}")
+    assert eq <= tol and ex <= tol
+
+
+def test_fp32_energy_gradient_against_direct_gradient(fmm):
+    """Plummer charges in (0,1]: FP32 forward + adjoint against the FP64
+    direct-sum gradient on a 4096-point subset.  theta = 0.5: at p = 8 the
+    Plummer tree needs it for 1e-4 on dE/dx (the FP64 oracle gives 1.1e-4
+    at theta = 0.6)."""
+    from oracle.gradient import energy_gradient_direct
+    n = 60000
+    _say(f"[fp32 gradient vs direct] plummer n={n}")
+    pos, q = workloads.plummer(n, 0)
+    sub = workloads.sample_targets(n, 4096, seed=3)
+    dq0, dx0 = energy_gradient_direct(pos, q, targets=sub)
+    pos_t = torch.from_numpy(pos).cuda().requires_grad_(True)
+    q_t = torch.from_numpy(q).cuda().float().requires_grad_(True)
+    plan = fmm.Plan(pos_t.detach(), p=8, leaf_max=128, splits=2, theta=0.5, precision="fp32")
+    E = fmm.fmm_energy(plan, q_t, pos_t)
+    gq, gx = torch.autograd.grad(E, (q_t, pos_t))
+    eq = _rel(gq.double().cpu().numpy()[sub], dq0)
+    ex = _rel(gx.double().cpu().numpy()[sub], dx0)
+    _say(f"    rel-L2 dE/dq {eq:.2e} dE/dx {ex:.2e}")
+    assert eq <= 1e-4 and ex <= 1e-4

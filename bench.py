@@ -5,11 +5,14 @@ Workload: N = 2^20 charges uniform in the unit cube, charges uniform in
 [-1, 1), expansion order p = 8, leaf size <= 128, potential and field.  A
 step is one evaluation pass (sort, P2M, M2M, M2L, L2L, L2P, P2P) of one
 charge vector on a cached plan (tree and lists built once, as in the
-paper's protocol), inputs resident in HBM.  ``value`` = N / step time in
-Mpoints/s.  The accuracy against the direct sum is measured on 8192
+paper's protocol), inputs resident in HBM, FP64.  ``value`` = N / step time
+in Mpoints/s.  ``variants`` times the other parts of the metric on the same
+workload: the FP32 form, and forward + backward (potential and field, then
+the adjoint giving dE/dq and dE/dx of E = 1/2 sum q u) in both precisions.
+Every variant's accuracy against the FP64 direct sum is measured on 8192
 sampled targets with the library's direct kernel; the roofline object
-reports the dominant kernel (per-stage HIP events over the timed steps);
-``cpu_baseline`` times the CPU oracle on a bounded sample.
+reports the dominant kernel of the headline pass (per-stage HIP events over
+the timed steps); ``cpu_baseline`` times the CPU oracle on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -87,10 +90,13 @@ def main():
     ap.add_argument("--leaf", type=int, default=128)
     ap.add_argument("--splits", type=int, default=3)
     ap.add_argument("--theta", type=float, default=0.7)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the headline (value) pass")
     ap.add_argument("--samples", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=1024)
+    ap.add_argument("--cpu-targets", type=int, default=2048)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the FP32 / forward+backward variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter scale)")
     args = ap.parse_args()
@@ -107,26 +113,89 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     pos, q = workloads.uniform_cube(args.n, 0)
-    tdt = torch.float64 if args.precision == "fp64" else torch.float32
     pos_d = torch.from_numpy(pos).to(dev)
-    q_d = torch.from_numpy(q).to(dev, tdt)
-    torch.cuda.synchronize()
+    q64 = torch.from_numpy(q).to(dev)
+    stream = torch.cuda.current_stream()
 
-    t0 = time.perf_counter()
-    plan = F.Plan(pos_d, p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
-                  precision=args.precision)
+    # FP64 direct sum at sampled targets: the accuracy reference of every variant
+    tg = workloads.sample_targets(args.n, args.samples, seed=1)
+    tg_d = torch.from_numpy(tg).to(dev)
+    ud, fd = F.direct(pos_d, q64, tg_d)
     torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
+    ud, fd = ud.cpu().numpy(), fd.cpu().numpy()
+    qs = q[tg]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def build(prec):
+        t0 = time.perf_counter()
+        plan = F.Plan(pos_d, p=args.p, leaf_max=args.leaf, splits=args.splits,
+                      theta=args.theta, precision=prec)
+        torch.cuda.synchronize()
+        return plan, (time.perf_counter() - t0) * 1e3
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    res_variants = {}
+
+    def run_forward(prec, profile):
+        plan, plan_ms = build(prec)
+        tdt = torch.float64 if prec == "fp64" else torch.float32
+        qd = q64.to(tdt)
+        pot = torch.empty((1, args.n), dtype=tdt, device=dev)
+        fld = torch.empty((1, args.n, 3), dtype=tdt, device=dev)
+        fn = lambda: plan.evaluate(qd, out=(pot, fld))
+        for _ in range(args.warmup):
+            fn()
+        if profile:
+            plan.set_profiling(True)
+        ms = timed(fn, args.steps, 0)
+        stages = None
+        if profile:
+            st_ms, passes = plan.read_profile()
+            plan.set_profiling(False)
+            stages = {k: v / max(passes, 1) for k, v in st_ms.items()}
+        up = pot[0].double().cpu().numpy()[tg]
+        fp = fld[0].double().cpu().numpy()[tg]
+        acc = {"rel_l2_pot": rel(up, ud), "rel_l2_field": rel(fp, fd)}
+        return plan, plan_ms, ms, stages, acc
+
+    def run_fwd_bwd(plan, prec):
+        tdt = torch.float64 if prec == "fp64" else torch.float32
+        qd = q64.to(tdt)
+        half = 0.5 * qd
+        out = {}
+
+        def fn():
+            u, f = plan.evaluate(qd)
+            gq, gx = plan.adjoint(qd, half, f)
+            out["u"], out["gq"], out["gx"] = u, gq, gx
+        ms = timed(fn, args.steps, args.warmup)
+        # E = 1/2 q.u-hat: dE/dq = u-hat/2 + G-hat^T(q/2), dE/dx = grad_x
+        dq = (0.5 * out["u"] + out["gq"]).double().cpu().numpy()[tg]
+        dx = out["gx"].double().cpu().numpy()[tg]
+        acc = {"rel_l2_dEdq": rel(dq, ud), "rel_l2_dEdx": rel(dx, -qs[:, None] * fd)}
+        return ms, acc
+
+    head = args.precision
+    plan, plan_ms, ms_per_step, per_stage, acc = run_forward(head, True)
     info = plan.info()
-    log(f"plan: {plan_ms:.1f} ms, depth {info['depth']}, M2L {info['n_m2l']}, "
+    value = args.n / (ms_per_step * 1e-3) / 1e6
+    log(f"plan ({head}): {plan_ms:.1f} ms, depth {info['depth']}, M2L {info['n_m2l']}, "
         f"P2P pairs {info['n_p2p']}, P2P interactions {info['p2p_interactions']}")
-
-    pot = torch.empty(args.n, dtype=tdt, device=dev)
-    fld = torch.empty((args.n, 3), dtype=tdt, device=dev)
-    out = (pot.view(1, -1), fld.view(1, -1, 3))
-    for _ in range(args.warmup):
-        plan.evaluate(q_d, out=out)
-    torch.cuda.synchronize()
+    log(f"fwd {head}: {ms_per_step:.3f} ms/step, {value:.1f} Mpoints/s, rel-L2 pot "
+        f"{acc['rel_l2_pot']:.2e} field {acc['rel_l2_field']:.2e}")
+    log("stages (ms/pass): " + ", ".join(f"{k} {v:.3f}" for k, v in per_stage.items()))
     if args.copy_calibration:
         a = torch.empty(1 << 25, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -134,44 +203,25 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    plan.set_profiling(True)
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.evaluate(q_d, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - w0) * 1e3
-    total_ms = ev0.elapsed_time(ev1)
-    stage_ms, passes = plan.read_profile()
-    plan.set_profiling(False)
-    ms_per_step = total_ms / args.steps
-    value = args.n / (ms_per_step * 1e-3) / 1e6
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall_ms / args.steps:.3f}), "
-        f"{value:.1f} Mpoints/s")
-    per_stage = {k: v / max(passes, 1) for k, v in stage_ms.items()}
-    log("stages (ms/pass): " + ", ".join(f"{k} {v:.3f}" for k, v in per_stage.items()))
+    if not args.only_headline:
+        ms, a2 = run_fwd_bwd(plan, head)
+        res_variants[f"fwd_bwd_{head}"] = {"ms_per_step": ms, "mpoints_s": args.n / ms / 1e3, **a2}
+        log(f"fwd+bwd {head}: {ms:.3f} ms/step, {args.n / ms / 1e3:.1f} Mpoints/s, {a2}")
+        other = "fp32" if head == "fp64" else "fp64"
+        del plan
+        plan2, pms2, ms2, _, acc2 = run_forward(other, False)
+        res_variants[f"fwd_{other}"] = {"ms_per_step": ms2, "mpoints_s": args.n / ms2 / 1e3,
+                                        "plan_build_ms": pms2, **acc2}
+        log(f"fwd {other}: {ms2:.3f} ms/step, {args.n / ms2 / 1e3:.1f} Mpoints/s, {acc2}")
+        ms3, a3 = run_fwd_bwd(plan2, other)
+        res_variants[f"fwd_bwd_{other}"] = {"ms_per_step": ms3, "mpoints_s": args.n / ms3 / 1e3, **a3}
+        log(f"fwd+bwd {other}: {ms3:.3f} ms/step, {args.n / ms3 / 1e3:.1f} Mpoints/s, {a3}")
+        del plan2
 
-    # accuracy against the direct sum (library's direct kernel, FP64)
-    tg = workloads.sample_targets(args.n, args.samples, seed=1)
-    tg_d = torch.from_numpy(tg).to(dev)
-    ud, fd = F.direct(pos_d, torch.from_numpy(q).to(dev), tg_d)
-    torch.cuda.synchronize()
-    ud, fd = ud.cpu().numpy(), fd.cpu().numpy()
-    up = pot.double().cpu().numpy()[tg]
-    fp = fld.double().cpu().numpy()[tg]
-    rel_pot = float(np.linalg.norm(up - ud) / np.linalg.norm(ud))
-    rel_fld = float(np.linalg.norm(fp - fd) / np.linalg.norm(fd))
-    log(f"rel-L2 vs direct on {args.samples} targets: pot {rel_pot:.3e}, field {rel_fld:.3e}")
-
-    # roofline of the dominant kernel (one launch per pass)
+    # roofline of the dominant kernel of the headline pass (one launch per pass)
     dom = max(per_stage, key=per_stage.get)
     K = (args.p + 1) ** 2
-    dtype = "f64" if args.precision == "fp64" else "f32"
+    dtype = "f64" if head == "fp64" else "f32"
     if dom == "p2p":
         flops = 20.0 * info["p2p_interactions"]
     elif dom == "l2p":
@@ -209,11 +259,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"uniform cube N={args.n}, charges U[-1,1), p={args.p}, "
                                f"leaf<={args.leaf}, s={args.splits}, theta={args.theta}, "
-                               f"potential+field, {args.precision}, cached plan",
+                               f"potential+field, {head} forward pass on a cached plan",
                    "n": args.n, "p": args.p, "leaf_max": args.leaf, "splits": args.splits,
-                   "theta": args.theta, "precision": args.precision},
-        "accuracy": {"rel_l2_pot": rel_pot, "rel_l2_field": rel_fld,
-                     "samples": args.samples, "reference": "direct sum (FP64)"},
+                   "theta": args.theta, "precision": head},
+        "accuracy": {**acc, "samples": args.samples, "reference": "direct sum (FP64)"},
+        "variants": res_variants,
         "stage_ms": per_stage,
         "plan_build_ms": plan_ms,
         "plan": {k: info[k] for k in ("depth", "nbox", "n_m2l", "n_p2p", "p2p_interactions")},

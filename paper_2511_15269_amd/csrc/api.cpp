@@ -111,6 +111,24 @@ void check_device(const fmm_plan* pl) {
     throw Error{FMM_EDEVICE, "current device differs from the plan's device"};
 }
 
+// Several charge vectors: FP32 plans built for more than one vector take
+// them kRB at a time through the multi-vector kernels; otherwise one pass
+// per vector.
+void run_vectors(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
+                 hipStream_t st) {
+  if (nrhs > 1 && pl->bq) {
+    const int W = batch_width();
+    const int64_t n = pl->n;
+    for (int r0 = 0; r0 < nrhs; r0 += W) {
+      const int R = std::min(W, nrhs - r0);
+      evaluate_batch(pl, dir, (const float*)q + (int64_t)r0 * n, R, (float*)pot + (int64_t)r0 * n,
+                     field ? (float*)field + 3 * (int64_t)r0 * n : nullptr, st);
+    }
+  } else {
+    evaluate(pl, dir, q, nrhs, pot, field, st);
+  }
+}
+
 }  // namespace
 }  // namespace fmm
 
@@ -166,6 +184,17 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
                         (size_t)std::max<int64_t>(
                             std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1));
       pl->field_t = plan_alloc(pl.get(), es * 3 * (size_t)n);
+      if (prm->precision == FMM_FP32 && prm->max_rhs > 1) {
+        const size_t W = (size_t)batch_width() * sizeof(float);
+        const size_t ni = (size_t)std::max<int64_t>(
+            std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
+        pl->bq = plan_alloc(pl.get(), W * n);
+        pl->bC = plan_alloc(pl.get(), W * K * pl->nbox);
+        pl->bD = plan_alloc(pl.get(), W * K * pl->nbox);
+        pl->bpart = plan_alloc(pl.get(), W * K * ni);
+        pl->bpot = plan_alloc(pl.get(), W * n);
+        pl->bfld = plan_alloc(pl.get(), W * 3 * n);
+      }
       pl->tables = get_tables(prm->p, prm->precision, pl->device);
       FMM_HIP(hipStreamSynchronize(st));
     } catch (...) {
@@ -201,7 +230,7 @@ fmm_status fmm_evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot,
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
-    fmm::evaluate(pl, 0, q, nrhs, pot, field, (hipStream_t)stream);
+    run_vectors(pl, 0, q, nrhs, pot, field, (hipStream_t)stream);
   });
 }
 
@@ -212,7 +241,7 @@ fmm_status fmm_evaluate_transposed(fmm_plan* pl, const void* q, int nrhs, void* 
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
-    fmm::evaluate(pl, 1, q, nrhs, pot, field, (hipStream_t)stream);
+    run_vectors(pl, 1, q, nrhs, pot, field, (hipStream_t)stream);
   });
 }
 

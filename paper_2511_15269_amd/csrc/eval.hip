@@ -35,278 +35,16 @@
 #include <cmath>
 
 #include "internal.h"
+#include "ops.h"
 #include "tables.h"
 
 namespace fmm {
 namespace {
 
-constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+using namespace ops;
 constexpr int kM2LThreads = 64;
 
-template <int P>
-struct K_ {
-  static constexpr int value = (P + 1) * (P + 1);
-};
-
-// Opaque copy of a wave-uniform pointer: table reads through it are issued
-// where they are used instead of being hoisted out of the interaction loop
-// (hoisting them all would exceed the scalar register file and spill).
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T*;  // constant memory
-
-template <typename T>
-__device__ __forceinline__ cptr<T> local_ptr(const T* p) {
-  asm volatile("" : "+s"(p));
-  return (cptr<T>)p;
-}
-
-// cos(m g), sin(m g), m = 0..P, by repeated complex multiplication
-template <int P, typename T>
-__device__ __forceinline__ void powers(T c1, T s1, T* c, T* s) {
-  c[0] = T(1);
-  s[0] = T(0);
-#pragma unroll
-  for (int m = 1; m <= P; ++m) {
-    c[m] = c[m - 1] * c1 - s[m - 1] * s1;
-    s[m] = s[m - 1] * c1 + c[m - 1] * s1;
-  }
-}
-
-// (v^m, v^{-m}) <- (a c + b s, b c - a s) for every degree, with
-// (c, s) = (cm[m], sgn * sm[m]) after the quarter-turn shift q (m*q*pi/2
-// added to the angle; q in {0, 1}): q = 1 maps (cos ma, sin ma) to
-// (cos m(pi/2 - a), sin m(pi/2 - a)).
-template <int P, typename T, int SGN, int Q>
-__device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
-#pragma unroll
-  for (int m = 1; m <= P; ++m) {
-    T c, s;
-    if (Q == 0) {
-      c = cm[m];
-      s = sm[m];
-    } else {
-      switch (m & 3) {
-        case 0: c = cm[m]; s = -sm[m]; break;
-        case 1: c = sm[m]; s = cm[m]; break;
-        case 2: c = -cm[m]; s = sm[m]; break;
-        default: c = -sm[m]; s = -cm[m]; break;
-      }
-    }
-    if (SGN < 0) s = -s;
-#pragma unroll
-    for (int n = m; n <= P; ++n) {
-      T a = v[cidx(n, m)], b = v[cidx(n, -m)];
-      v[cidx(n, m)] = a * c + b * s;
-      v[cidx(n, -m)] = b * c - a * s;
-    }
-  }
-}
-
-// v_n <- Y_n v_n (TR: Y_n^T v_n) over the stored nonzero entries
-template <int P, bool TR, typename T>
-__device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
-#pragma unroll
-  for (int n = 1; n <= P; ++n) {
-    cptr<T> Y = local_ptr(tab) + (TR ? tab_yt(P) : tab_y(P)) + ycbase(n);
-    T u[2 * P + 1];
-    int o = 0;
-#pragma unroll
-    for (int a = -n; a <= n; ++a) {
-      T acc = T(0);
-#pragma unroll
-      for (int b = -n; b <= n; ++b) {
-        if (!ynz(n, a, b)) continue;
-        acc = fma(Y[o], v[cidx(n, b)], acc);
-        ++o;
-      }
-      u[a + n] = acc;
-    }
-#pragma unroll
-    for (int a = -n; a <= n; ++a) v[cidx(n, a)] = u[a + n];
-  }
-}
-
-enum { kM2M = 0, kM2L = 1, kL2L = 2 };
-
-// z-axis operators of App. B.3 in the normalised, radius-scaled basis, in
-// place.  With r the shift length:
-//   M2L (a = rho_src/r, b = rho_tgt/r):   out_n = b^{n+1} sum_k T_nk a^k v_k
-//   M2M (a = r/rho_par, b = rho_chi/rho_par): out_n = sum_{k<=n} T_nk a^{n-k} b^k v_k
-//   L2L (a = r/rho_par, b = rho_chi/rho_par): out_n = b^{n+1} sum_{k>=n} T_nk a^{k-n} v_k
-template <int P, int KIND, typename T>
-__device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab) {
-  T pa[2 * P + 2], pb[P + 2];
-  pa[0] = T(1);
-  pb[0] = T(1);
-#pragma unroll
-  for (int j = 1; j <= P; ++j) pa[j] = pa[j - 1] * a;
-#pragma unroll
-  for (int j = 1; j <= P + 1; ++j) pb[j] = pb[j - 1] * b;
-  if (KIND == kM2L) {
-#pragma unroll
-    for (int n = 0; n <= P; ++n)
-#pragma unroll
-      for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pa[n];
-#pragma unroll
-    for (int m = -P; m <= P; ++m) {
-      const int am = m < 0 ? -m : m;
-      cptr<T> tb = local_ptr(tab) + tab_tm2l(P) + zl_base(P, am);
-      T o[P + 1];
-      int c = 0;
-#pragma unroll
-      for (int n = am; n <= P; ++n) {
-        T acc = T(0);
-#pragma unroll
-        for (int k = am; k <= P; ++k) acc = fma(tb[c++], v[cidx(k, m)], acc);
-        o[n] = acc * pb[n + 1];
-      }
-#pragma unroll
-      for (int n = am; n <= P; ++n) v[cidx(n, m)] = m < 0 ? -o[n] : o[n];
-    }
-  } else {
-    if (KIND == kM2M) {
-#pragma unroll
-      for (int n = 0; n <= P; ++n)
-#pragma unroll
-        for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pb[n];
-    }
-#pragma unroll
-    for (int m = -P; m <= P; ++m) {
-      const int am = m < 0 ? -m : m;
-      cptr<T> tb = local_ptr(tab) + (KIND == kM2M ? tab_tm2m(P) : tab_tl2l(P)) + zt_base(P, am);
-      T o[P + 1];
-      int c = 0;
-#pragma unroll
-      for (int n = am; n <= P; ++n) {
-        T acc = T(0);
-        if (KIND == kM2M) {
-#pragma unroll
-          for (int k = am; k <= n; ++k) acc = fma(tb[c++] * pa[n - k], v[cidx(k, m)], acc);
-        } else {
-#pragma unroll
-          for (int k = n; k <= P; ++k) acc = fma(tb[c++] * pa[k - n], v[cidx(k, m)], acc);
-          acc *= pb[n + 1];
-        }
-        o[n] = acc;
-      }
-#pragma unroll
-      for (int n = am; n <= P; ++n) v[cidx(n, m)] = o[n];
-    }
-  }
-}
-
-// Rotate so that b points along +z, shift along z, rotate back.
-// b = old centre - new centre; rho_old, rho_new the scale lengths of the
-// two boxes.  M2L maps multipole (regular-basis sign convention) to local
-// (singular-basis convention); M2M keeps the former, L2L the latter.
-template <int P, int KIND, typename T>
-__device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double bz,
-                                             double rho_old, double rho_new,
-                                             const T* __restrict__ tab) {
-  const double rxy2 = bx * bx + by * by;
-  const double rxy = sqrt(rxy2);
-  const double r = sqrt(rxy2 + bz * bz);
-  double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
-  if (rxy > 0.0) {
-    ca = bx / rxy;
-    sa = by / rxy;
-  }
-  if (r > 0.0) {
-    cb = bz / r;
-    sb = rxy / r;
-  }
-  double a, b;
-  if (KIND == kM2L) {
-    a = rho_old / r;
-    b = rho_new / r;
-  } else if (KIND == kM2M) {
-    a = r / rho_new;
-    b = rho_old / rho_new;
-  } else {
-    a = r / rho_old;
-    b = rho_new / rho_old;
-  }
-  T am_c[P + 1], am_s[P + 1], bm_c[P + 1], bm_s[P + 1];
-  powers<P, T>(T(ca), T(sa), am_c, am_s);
-  powers<P, T>(T(cb), T(sb), bm_c, bm_s);
-  // forward: Rz(pi/2 - A), Y, Rz(-B), Y^T   (sign conventions per kind)
-  if (KIND == kL2L)
-    azimuth<P, T, -1, 1>(v, am_c, am_s);
-  else
-    azimuth<P, T, +1, 1>(v, am_c, am_s);
-  apply_y<P, false, T>(v, tab);
-  if (KIND == kL2L)
-    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
-  else
-    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
-  apply_y<P, true, T>(v, tab);
-  zshift<P, KIND, T>(v, T(a), T(b), tab);
-  // back: Y, Rz(B), Y^T, Rz(A - pi/2)
-  apply_y<P, false, T>(v, tab);
-  if (KIND == kM2M)
-    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
-  else
-    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
-  apply_y<P, true, T>(v, tab);
-  if (KIND == kM2M)
-    azimuth<P, T, -1, 1>(v, am_c, am_s);
-  else
-    azimuth<P, T, +1, 1>(v, am_c, am_s);
-}
-
-// Source points in leaf order with their charges, one 32-byte record per
-// point (so that a wave-uniform read is a single scalar load).  Positions
-// stay FP64 in both forms: the FP32 form takes each pair difference in FP64
-// and rounds it, so clustered points keep their separation and exactly
-// coincident points give exactly zero.
-template <typename T>
-struct alignas(32) Src {
-  double x, y, z;
-  T q;
-};
-
 // ---------------------------------------------------------------- P2M
-// Regular basis R-hat^m_n(x, y, z) in degree-major order by the App. A.1
-// recursions; calls f(k, value) for k = 0..K-1 as values become available.
-template <int P, typename T, typename F>
-__device__ __forceinline__ void regular_basis(T x, T y, T z, F&& f) {
-  const T r2 = x * x + y * y + z * z;
-  T sc = T(1), ss = T(0);  // sectoral R^{m}_{m}, R^{-m}_{m}
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-    if (m == 1) {
-      sc = x * T(0.5);
-      ss = -y * T(0.5);
-    } else if (m >= 2) {
-      const T nc = (x * sc + y * ss) * T(1.0 / (2 * m));
-      const T ns = (x * ss - y * sc) * T(1.0 / (2 * m));
-      sc = nc;
-      ss = ns;
-    }
-    f(cidx(m, m), sc);
-    if (m > 0) f(cidx(m, -m), ss);
-    T p2c = T(0), p2s = T(0), p1c = sc, p1s = ss;
-#pragma unroll
-    for (int n = m + 1; n <= P; ++n) {
-      T c, s;
-      if (n == m + 1) {
-        c = z * p1c;
-        s = z * p1s;
-      } else {
-        const T inv = T(1.0 / ((n - m) * (n + m)));
-        c = (T(2 * n - 1) * z * p1c - r2 * p2c) * inv;
-        s = (T(2 * n - 1) * z * p1s - r2 * p2s) * inv;
-      }
-      f(cidx(n, m), c);
-      if (m > 0) f(cidx(n, -m), s);
-      p2c = p1c;
-      p2s = p1s;
-      p1c = c;
-      p1s = s;
-    }
-  }
-}
-
 // C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole)
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(
@@ -436,89 +174,6 @@ __global__ __launch_bounds__(64) void k_l2l(
 }
 
 // ---------------------------------------------------------------- L2P
-// Regular basis and its gradient (App. A.1, A.3; the sectoral gradient
-// without the printed leading minus), accumulated against w[k] = weight *
-// local coefficient: pot += w R, grad += w grad R.
-template <int P, typename T>
-__device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ w,
-                                           T& pot, T& gx, T& gy, T& gz) {
-  const T r2 = x * x + y * y + z * z;
-  // sectoral value and gradient (z component of a sectoral gradient is 0)
-  T sc = T(1), ss = T(0), scx = T(0), scy = T(0), ssx = T(0), ssy = T(0);
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-    if (m == 1) {
-      sc = x * T(0.5);
-      ss = -y * T(0.5);
-      scx = T(0.5);
-      scy = T(0);
-      ssx = T(0);
-      ssy = T(-0.5);
-    } else if (m >= 2) {
-      const T f = T(1.0 / (2 * m));
-      const T nc = (x * sc + y * ss) * f;
-      const T ns = (x * ss - y * sc) * f;
-      const T ncx = (x * scx + y * ssx + sc) * f;
-      const T ncy = (x * scy + y * ssy + ss) * f;
-      const T nsx = (x * ssx - y * scx + ss) * f;
-      const T nsy = (x * ssy - y * scy - sc) * f;
-      sc = nc; ss = ns; scx = ncx; scy = ncy; ssx = nsx; ssy = nsy;
-    }
-    {
-      const T wc = w[cidx(m, m)];
-      pot = fma(wc, sc, pot);
-      gx = fma(wc, scx, gx);
-      gy = fma(wc, scy, gy);
-      if (m > 0) {
-        const T ws = w[cidx(m, -m)];
-        pot = fma(ws, ss, pot);
-        gx = fma(ws, ssx, gx);
-        gy = fma(ws, ssy, gy);
-      }
-    }
-    // previous two degrees for +m (c) and -m (s): value, gradient
-    T c2 = T(0), c2x = T(0), c2y = T(0), c2z = T(0);
-    T s2 = T(0), s2x = T(0), s2y = T(0), s2z = T(0);
-    T c1 = sc, c1x = scx, c1y = scy, c1z = T(0);
-    T s1 = ss, s1x = ssx, s1y = ssy, s1z = T(0);
-#pragma unroll
-    for (int n = m + 1; n <= P; ++n) {
-      T c, cxg, cyg, czg, s, sxg, syg, szg;
-      if (n == m + 1) {
-        c = z * c1; cxg = z * c1x; cyg = z * c1y; czg = z * c1z + c1;
-        s = z * s1; sxg = z * s1x; syg = z * s1y; szg = z * s1z + s1;
-      } else {
-        const T inv = T(1.0 / ((n - m) * (n + m)));
-        const T a = T(2 * n - 1);
-        c = (a * z * c1 - r2 * c2) * inv;
-        cxg = (a * (z * c1x) - r2 * c2x - T(2) * c2 * x) * inv;
-        cyg = (a * (z * c1y) - r2 * c2y - T(2) * c2 * y) * inv;
-        czg = (a * (z * c1z + c1) - r2 * c2z - T(2) * c2 * z) * inv;
-        s = (a * z * s1 - r2 * s2) * inv;
-        sxg = (a * (z * s1x) - r2 * s2x - T(2) * s2 * x) * inv;
-        syg = (a * (z * s1y) - r2 * s2y - T(2) * s2 * y) * inv;
-        szg = (a * (z * s1z + s1) - r2 * s2z - T(2) * s2 * z) * inv;
-      }
-      const T wc = w[cidx(n, m)];
-      pot = fma(wc, c, pot);
-      gx = fma(wc, cxg, gx);
-      gy = fma(wc, cyg, gy);
-      gz = fma(wc, czg, gz);
-      if (m > 0) {
-        const T ws = w[cidx(n, -m)];
-        pot = fma(ws, s, pot);
-        gx = fma(ws, sxg, gx);
-        gy = fma(ws, syg, gy);
-        gz = fma(ws, szg, gz);
-      }
-      c2 = c1; c2x = c1x; c2y = c1y; c2z = c1z;
-      s2 = s1; s2x = s1x; s2y = s1y; s2z = s1z;
-      c1 = c; c1x = cxg; c1y = cyg; c1z = czg;
-      s1 = s; s1x = sxg; s1y = syg; s1z = szg;
-    }
-  }
-}
-
 // L2P: u = -1/(4 pi) (1/rho) sum w_m D R-hat(y), y = (x - c)/rho, and
 // field = -grad u (an extra 1/rho from the chain rule), at every point of the
 // target leaf; writes (not adds) the outputs in input order.
@@ -553,22 +208,6 @@ __global__ __launch_bounds__(64) void k_l2p(
       field[3 * (int64_t)o + 2] = ff * fz;
     }
   }
-}
-
-// ---------------------------------------------------------------- P2P
-__device__ __forceinline__ double inv_sqrt(double r2) {
-  // hardware estimate refined by one Newton step
-  const double y = __builtin_amdgcn_rsq(r2);
-  return y * fma(-0.5 * r2, y * y, 1.5);
-}
-__device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
-
-// Neumaier's compensated addition: s + c carries the running sum.
-template <typename T>
-__device__ __forceinline__ void neumaier(T& s, T& c, T x) {
-  const T t = s + x;
-  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-  s = t;
 }
 
 // One source point against the lane's target at (xi, yi, zi): the

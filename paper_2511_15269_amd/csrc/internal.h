@@ -96,6 +96,13 @@ struct fmm_plan {
   void* D = nullptr;         // [nbox][K]   locals (normalised)
   void* partial = nullptr;   // [max n_items][K] M2L partial sums
   void* field_t = nullptr;   // [n][3] field of the transposed pass (adjoint)
+  // multi-vector workspace (FP32 plans with max_rhs > 1), vectors innermost
+  void* bq = nullptr;     // [n][32]
+  void* bC = nullptr;     // [nbox][K][32]
+  void* bD = nullptr;     // [nbox][K][32]
+  void* bpart = nullptr;  // [max n_items][K][32]
+  void* bpot = nullptr;   // [n][32]
+  void* bfld = nullptr;   // [n][3][32]
   const void* tables = nullptr;  // device operator tables for (p, precision)
 
   std::vector<fmm::DevBuf> bufs;
@@ -121,6 +128,10 @@ const void* get_tables(int p, int precision, int device);
 // Evaluation (eval.hip): dir 0 = G-hat, dir 1 = G-hat^T.
 void evaluate(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
               hipStream_t st);
+// Up to batch_width() FP32 charge vectors in one pass (batch.hip).
+int batch_width();
+void evaluate_batch(fmm_plan* pl, int dir, const float* q, int R, float* pot, float* field,
+                    hipStream_t st);
 // Adjoint combine: grad_x = -(g * field_fwd + q * field_t) (eval.hip).
 void adjoint_combine(fmm_plan* pl, const void* q, const void* g, const void* field_fwd,
                      const void* field_t, void* grad_x, hipStream_t st);

@@ -296,3 +296,43 @@ def test_fp32_energy_gradient_against_direct_gradient(fmm):
     ex = _rel(gx.double().cpu().numpy()[sub], dx0)
     _say(f"    rel-L2 dE/dq {eq:.2e} dE/dx {ex:.2e}")
     assert eq <= 1e-4 and ex <= 1e-4
+
+
+BATCH_CASES = [
+    # kind, n, p, leaf, s, theta, R
+    ("cube", 20000, 8, 128, 2, 0.7, 32),
+    ("cube", 9000, 6, 64, 3, 0.6, 5),
+    ("cluster", 15000, 10, 128, 2, 0.6, 40),   # two passes: 32 + 8 vectors
+    ("cube", 100, 4, 128, 2, 0.6, 3),          # one box, direct only
+]
+
+
+@pytest.mark.parametrize("kind,n,p,leaf,s,theta,R", BATCH_CASES)
+def test_batched_vectors_match_single_runs_and_oracle(fmm, kind, n, p, leaf, s, theta, R):
+    """R charge vectors in one multi-vector pass (FP32, MFMA near field)
+    equal R single-vector passes to 1e-6 and the FP64 oracle to 1e-5."""
+    from oracle.fmm import fmm as oracle_fmm
+    _say(f"[batched] {kind} n={n} p={p} leaf={leaf} s={s} theta={theta} R={R}")
+    pos, _ = _inputs(kind, n, 19)
+    Q = np.random.default_rng(20).uniform(-1, 1, (R, n))
+    pt = torch.from_numpy(pos).cuda()
+    plan = fmm.Plan(pt, p=p, leaf_max=leaf, splits=s, theta=theta, precision="fp32", max_rhs=R)
+    single = fmm.Plan(pt, p=p, leaf_max=leaf, splits=s, theta=theta, precision="fp32")
+    Qt = torch.from_numpy(Q).cuda().float()
+    U, Fd = plan.evaluate(Qt)
+    worst = 0.0
+    for r in range(R):
+        u1, f1 = single.evaluate(Qt[r])
+        worst = max(worst, _rel(U[r].double().cpu().numpy(), u1.double().cpu().numpy()),
+                    _rel(Fd[r].double().cpu().numpy(), f1.double().cpu().numpy()))
+    _say(f"    batched vs single: {worst:.2e}")
+    assert worst <= 1e-6
+    for r in (0, R - 1):
+        u0, f0 = oracle_fmm(pos, Q[r], p, leaf, s, theta)
+        eu = _rel(U[r].double().cpu().numpy(), u0)
+        ef = _rel(Fd[r].double().cpu().numpy(), f0)
+        _say(f"    vector {r} vs oracle: pot {eu:.2e} field {ef:.2e}")
+        assert eu <= 1e-5 and ef <= 1e-5
+    Ut, _ = plan.evaluate_transposed(Qt)
+    ut1, _ = single.evaluate_transposed(Qt[R - 1])
+    assert _rel(Ut[R - 1].double().cpu().numpy(), ut1.double().cpu().numpy()) <= 1e-6

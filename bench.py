@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=2048)
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the FP32 / forward+backward variants")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the multi-vector and uneven-problem-set variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter scale)")
     args = ap.parse_args()
@@ -217,6 +219,9 @@ def main():
         res_variants[f"fwd_bwd_{other}"] = {"ms_per_step": ms3, "mpoints_s": args.n / ms3 / 1e3, **a3}
         log(f"fwd+bwd {other}: {ms3:.3f} ms/step, {args.n / ms3 / 1e3:.1f} Mpoints/s, {a3}")
         del plan2
+    if not args.only_headline and not args.no_batched:
+        res_variants.update(run_batched(F, torch, dev, args, timed, rel))
+        res_variants.update(run_uneven(F, torch, dev, args, timed, rel))
 
     # roofline of the dominant kernel of the headline pass (one launch per pass)
     dom = max(per_stage, key=per_stage.get)
@@ -271,6 +276,97 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def run_batched(F, torch, dev, args, timed, rel, n=1 << 18, R=32):
+    """One geometry, R charge vectors per pass (FP32): multi-vector pass
+    against R single-vector passes, in point-evaluations per second."""
+    import workloads
+    pos, Q = workloads.uniform_cube(n, 0, nrhs=R)
+    pos_d = torch.from_numpy(pos).to(dev)
+    Qd = torch.from_numpy(Q).to(dev).float()
+    kw = dict(p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
+              precision="fp32")
+    plan = F.Plan(pos_d, max_rhs=R, **kw)
+    single = F.Plan(pos_d, **kw)
+    pot = torch.empty((R, n), dtype=torch.float32, device=dev)
+    fld = torch.empty((R, n, 3), dtype=torch.float32, device=dev)
+    ms_b = timed(lambda: plan.evaluate(Qd, out=(pot, fld)), args.steps, args.warmup)
+    p1 = torch.empty((1, n), dtype=torch.float32, device=dev)
+    f1 = torch.empty((1, n, 3), dtype=torch.float32, device=dev)
+
+    def singles():
+        for r in range(R):
+            single.evaluate(Qd[r:r + 1], out=(p1, f1))
+    ms_s = timed(singles, max(1, args.steps // 4), 1)
+    tg = workloads.sample_targets(n, 2048, seed=1)
+    tg_d = torch.from_numpy(tg).to(dev)
+    acc = {}
+    for r in (0, R - 1):
+        ud, fd = F.direct(pos_d, torch.from_numpy(Q[r]).to(dev), tg_d)
+        acc[f"rel_l2_pot_v{r}"] = rel(pot[r].double().cpu().numpy()[tg], ud.cpu().numpy())
+        acc[f"rel_l2_field_v{r}"] = rel(fld[r].double().cpu().numpy()[tg], fd.cpu().numpy())
+    out = {
+        f"fwd_fp32_batched{R}_n{n}": {"ms_per_step": ms_b, "mpoints_s": R * n / ms_b / 1e3,
+                                      "vectors": R, **acc},
+        f"fwd_fp32_{R}x_single_n{n}": {"ms_per_step": ms_s, "mpoints_s": R * n / ms_s / 1e3,
+                                       "vectors": R},
+    }
+    log(f"batched {R}x{n} fp32: {ms_b:.3f} ms ({R * n / ms_b / 1e3:.1f} Mpoints/s); "
+        f"{R} single passes {ms_s:.3f} ms ({R * n / ms_s / 1e3:.1f}); {acc}")
+    return out
+
+
+def run_uneven(F, torch, dev, args, timed, rel, k=16):
+    """Sixteen independent uniform-cube problems of log-uniform sizes in
+    [1e4, 5e5] (FP32): one plan over all of them replayed as a captured
+    graph, against the same plan launched eagerly and against separate
+    plans evaluated one after another."""
+    import workloads
+    sizes = workloads.uneven_problem_sizes(k, seed=100)
+    parts = [workloads.uniform_cube(m, 101 + j) for j, m in enumerate(sizes)]
+    pos = np.concatenate([a for a, _ in parts])
+    q = np.concatenate([b for _, b in parts])
+    N = len(pos)
+    pos_d = torch.from_numpy(pos).to(dev)
+    qd = torch.from_numpy(q).to(dev).float()
+    kw = dict(p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
+              precision="fp32")
+    plan = F.Plan(pos_d, sizes=sizes, **kw)
+    qg = qd.reshape(1, N).clone()
+    g = F.Graph(plan, qg, field=True)
+    ms_g = timed(g.launch, args.steps, args.warmup)
+    pot = torch.empty((1, N), dtype=torch.float32, device=dev)
+    fld = torch.empty((1, N, 3), dtype=torch.float32, device=dev)
+    ms_e = timed(lambda: plan.evaluate(qg, out=(pot, fld)), args.steps, args.warmup)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    seps = [F.Plan(pos_d[off[j]:off[j + 1]], **kw) for j in range(k)]
+    outs = [(torch.empty((1, m), dtype=torch.float32, device=dev),
+             torch.empty((1, m, 3), dtype=torch.float32, device=dev)) for m in sizes]
+
+    def separate():
+        for j in range(k):
+            seps[j].evaluate(qg[:, off[j]:off[j + 1]].contiguous(), out=outs[j])
+    ms_s = timed(separate, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    eu = ef = 0.0
+    for j in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        tg = workloads.sample_targets(sizes[j], 1024, seed=1)
+        ud, fd = F.direct(pos_d[off[j]:off[j + 1]],
+                          torch.from_numpy(parts[j][1]).to(dev), torch.from_numpy(tg).to(dev))
+        eu = max(eu, rel(g.pot[0, off[j] + tg].double().cpu().numpy(), ud.cpu().numpy()))
+        ef = max(ef, rel(g.field[0, off[j] + tg].double().cpu().numpy(), fd.cpu().numpy()))
+    same = bool(torch.equal(g.pot, pot) and torch.equal(g.field, fld))
+    out = {
+        f"fwd_fp32_uneven{k}_graph": {"ms_per_step": ms_g, "mpoints_s": N / ms_g / 1e3,
+                                      "n_total": N, "sizes": sizes, "rel_l2_pot_max": eu,
+                                      "rel_l2_field_max": ef, "graph_equals_eager": same},
+        f"fwd_fp32_uneven{k}_eager": {"ms_per_step": ms_e, "mpoints_s": N / ms_e / 1e3},
+        f"fwd_fp32_uneven{k}_separate_plans": {"ms_per_step": ms_s, "mpoints_s": N / ms_s / 1e3},
+    }
+    log(f"uneven {k} problems (N={N}) fp32: graph {ms_g:.3f} ms ({N / ms_g / 1e3:.1f} Mpoints/s), "
+        f"eager {ms_e:.3f} ms, separate plans {ms_s:.3f} ms; rel-L2 pot {eu:.2e} field {ef:.2e}")
+    return out
 
 
 def m2l_flops(p: int) -> float:

@@ -109,6 +109,26 @@ const char* fmm_last_error(void);
 fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
                            void* stream, fmm_plan** out);
 
+/* One plan over several independent problems of uneven sizes (beyond the
+ * paper, which treats one system per hierarchy; each problem's tree and
+ * lists follow Sec. II.A-II.B unchanged).
+ *   pos      device, double[offsets[nprob]][3]: the points of problem k are
+ *            rows offsets[k] .. offsets[k+1]-1.  Read only, copied.
+ *   offsets  host, int64[nprob+1], offsets[0] = 0, strictly increasing
+ *            (every problem has at least one point); total below 2^31.
+ *   nprob    number of problems, >= 1.
+ * Each problem gets its own tree and lists, exactly those fmm_plan_create
+ * would build for its points alone (depths may differ); problems never
+ * interact.  The plan then behaves as a plan of offsets[nprob] points:
+ * every call below takes charges and returns potentials/fields for the
+ * concatenated points, and each evaluation stage covers all problems in
+ * one launch (M2M and L2L: one launch per level step, the deepest tree
+ * setting the count).  fmm_plan_get_tree/get_lists report global box and
+ * leaf numbering: problem k's boxes follow those of problems 0..k-1.
+ * Errors: as fmm_plan_create, plus FMM_EINVAL for bad offsets. */
+fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int nprob,
+                                 const fmm_params* prm, void* stream, fmm_plan** out);
+
 /* Sizes of the plan (host struct, written on success). */
 fmm_status fmm_plan_get_info(const fmm_plan* plan, fmm_plan_info* info);
 
@@ -201,6 +221,29 @@ fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
 
 /* Release the plan and its device memory (NULL is accepted). */
 fmm_status fmm_plan_destroy(fmm_plan* plan);
+
+/* A whole evaluation captured once as a HIP graph and replayed with one
+ * launch call (the sequence of stage kernels of fmm_evaluate, or of
+ * fmm_evaluate_transposed when `transposed` is nonzero, for fixed buffers).
+ *   plan   the plan; must outlive the graph and must not be destroyed or
+ *          evaluated concurrently with a replay.  Stage profiling is not
+ *          recorded inside graphs.
+ *   q, pot, field, nrhs   as for fmm_evaluate; the graph keeps these device
+ *          addresses: each replay reads q's current contents and rewrites
+ *          pot (and field).
+ *   out    host, receives the graph (free with fmm_graph_destroy).
+ * Nothing runs at creation.  The graph contains kernel launches only.
+ * Errors: as fmm_evaluate, FMM_EDEVICE if capture or instantiation fails. */
+typedef struct fmm_graph fmm_graph;
+fmm_status fmm_graph_create(fmm_plan* plan, int transposed, const void* q, int nrhs,
+                            void* pot, void* field, fmm_graph** out);
+
+/* Enqueue one replay on `stream`.  Errors: FMM_EINVAL (NULL graph),
+ * FMM_EDEVICE. */
+fmm_status fmm_graph_launch(fmm_graph* graph, void* stream);
+
+/* Release the graph (NULL is accepted). */
+fmm_status fmm_graph_destroy(fmm_graph* graph);
 
 #ifdef __cplusplus
 }

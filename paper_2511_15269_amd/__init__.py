@@ -19,7 +19,8 @@ import torch
 from ._lib import (FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
                    STAGES, FMMError, FmmParams, FmmPlanInfo, check, lib)
 
-__all__ = ["Plan", "FMMError", "params", "direct", "STAGES", "FMMPotential", "fmm_energy"]
+__all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotential",
+           "fmm_energy"]
 
 
 def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = None,
@@ -62,10 +63,15 @@ def _stream_ptr(stream):
 
 class Plan:
     """Tree, geometry and interaction lists of a fixed point set (the
-    paper's cached hierarchy), reusable for any number of charge vectors."""
+    paper's cached hierarchy), reusable for any number of charge vectors.
+
+    With ``sizes`` (problem sizes summing to N), ``pos`` holds several
+    independent problems back to back; each gets its own tree and lists and
+    every evaluation covers all of them at once (fmm_multi_plan_create)."""
 
     def __init__(self, pos: torch.Tensor, p=8, leaf_max=128, splits=2, theta=0.7,
-                 max_depth=16, precision="fp64", tie="source", max_rhs=1, stream=None):
+                 max_depth=16, precision="fp64", tie="source", max_rhs=1, stream=None,
+                 sizes=None):
         if not (isinstance(pos, torch.Tensor) and pos.is_cuda):
             raise ValueError("pos must be a CUDA tensor")
         if pos.dim() != 2 or pos.shape[1] != 3:
@@ -78,9 +84,19 @@ class Plan:
         self._prm = params(p, leaf_max, splits, theta, max_depth, precision, tie, max_rhs)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(lib().fmm_plan_create(ctypes.c_void_p(pos.data_ptr()), self.n,
-                                        ctypes.byref(self._prm), _stream_ptr(stream),
-                                        ctypes.byref(self._h)))
+            if sizes is None:
+                check(lib().fmm_plan_create(ctypes.c_void_p(pos.data_ptr()), self.n,
+                                            ctypes.byref(self._prm), _stream_ptr(stream),
+                                            ctypes.byref(self._h)))
+            else:
+                off = np.concatenate([[0], np.cumsum(np.asarray(sizes, np.int64))])
+                if off[-1] != self.n:
+                    raise ValueError("sizes must sum to the number of points")
+                self.offsets = off
+                check(lib().fmm_multi_plan_create(
+                    ctypes.c_void_p(pos.data_ptr()),
+                    off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
+                    ctypes.byref(self._prm), _stream_ptr(stream), ctypes.byref(self._h)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -203,6 +219,43 @@ class Plan:
         with torch.cuda.device(self.device):
             check(lib().fmm_plan_get_lists(self._h, *[x.ctypes.data_as(P64) for x in a]))
         return tuple(a)
+
+
+class Graph:
+    """One evaluation of ``plan`` captured as a HIP graph for fixed buffers
+    (fmm_graph_create): ``launch()`` replays it, reading ``q``'s current
+    contents and rewriting ``pot`` (and ``field``)."""
+
+    def __init__(self, plan: Plan, q: torch.Tensor, field: bool = True,
+                 transposed: bool = False):
+        self.plan = plan
+        self.q = plan._vec(q, "q")
+        if self.q.data_ptr() != q.data_ptr():
+            raise ValueError("q must be contiguous (the graph keeps its address)")
+        R = self.q.shape[0]
+        self.pot = torch.empty((R, plan.n), dtype=plan.dtype, device=q.device)
+        self.field = (torch.empty((R, plan.n, 3), dtype=plan.dtype, device=q.device)
+                      if field else None)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            check(lib().fmm_graph_create(
+                plan._h, 1 if transposed else 0, ctypes.c_void_p(self.q.data_ptr()), R,
+                ctypes.c_void_p(self.pot.data_ptr()),
+                ctypes.c_void_p(self.field.data_ptr()) if self.field is not None else None,
+                ctypes.byref(self._h)))
+
+    def launch(self, stream=None) -> None:
+        with torch.cuda.device(self.plan.device):
+            check(lib().fmm_graph_launch(self._h, _stream_ptr(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().fmm_graph_destroy(h)
+            except Exception:
+                pass
+            self._h = None
 
 
 class FMMPotential(torch.autograd.Function):

@@ -62,10 +62,17 @@ def lib() -> ctypes.CDLL:
         L.fmm_adjoint.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp, vp]
         L.fmm_plan_set_profiling.argtypes = [vp, ctypes.c_int]
         L.fmm_plan_read_profile.argtypes = [vp, dp, i64p]
+        L.fmm_multi_plan_create.argtypes = [vp, i64p, ctypes.c_int, ctypes.POINTER(FmmParams),
+                                            vp, ctypes.POINTER(vp)]
+        L.fmm_graph_create.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp,
+                                       ctypes.POINTER(vp)]
+        L.fmm_graph_launch.argtypes = [vp, vp]
+        L.fmm_graph_destroy.argtypes = [vp]
         for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
                   "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy",
                   "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile",
-                  "fmm_evaluate_transposed", "fmm_adjoint"):
+                  "fmm_evaluate_transposed", "fmm_adjoint", "fmm_multi_plan_create",
+                  "fmm_graph_create", "fmm_graph_launch", "fmm_graph_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

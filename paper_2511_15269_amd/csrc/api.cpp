@@ -54,6 +54,62 @@ void plan_free_all(fmm_plan* pl) {
   pl->device_bytes = 0;
 }
 
+void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st) {
+  const int s = pl->s;
+  int Lmax = 0;
+  for (const TreeDesc& t : trees) Lmax = std::max(Lmax, t.L);
+  auto upload = [&](const std::vector<int32_t>& v) {
+    int32_t* d = (int32_t*)plan_alloc(pl, sizeof(int32_t) * v.size());
+    if (!v.empty())
+      FMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st));
+    FMM_HIP(hipStreamSynchronize(st));
+    return d;
+  };
+  std::vector<int32_t> lb;
+  for (const TreeDesc& t : trees) {
+    const int64_t nl = t.level_off[t.L + 1] - t.level_off[t.L];
+    for (int64_t i = 0; i < nl; ++i) lb.push_back((int32_t)(t.box_base + t.level_off[t.L] + i));
+  }
+  pl->leaf_box = upload(lb);
+  pl->m2m_steps.clear();
+  pl->l2l_steps.clear();
+  // Upward: step h takes the parents h+1 levels above each tree's leaves.
+  for (int h = 0; h < Lmax; ++h) {
+    std::vector<int32_t> a, b;
+    for (const TreeDesc& t : trees) {
+      const int l = t.L - 1 - h;
+      if (l < 0) continue;
+      const int64_t np = t.level_off[l + 1] - t.level_off[l];
+      for (int64_t i = 0; i < np; ++i) {
+        a.push_back((int32_t)(t.box_base + t.level_off[l] + i));
+        b.push_back((int32_t)(t.box_base + t.level_off[l + 1] + (i << s)));
+      }
+    }
+    Step S;
+    S.n = (int64_t)a.size();
+    S.a = upload(a);
+    S.b = upload(b);
+    pl->m2m_steps.push_back(S);
+  }
+  // Downward: step l takes level l of every tree that deep.
+  for (int l = 0; l <= Lmax; ++l) {
+    std::vector<int32_t> a, b;
+    for (const TreeDesc& t : trees) {
+      if (l > t.L) continue;
+      const int64_t nb = t.level_off[l + 1] - t.level_off[l];
+      for (int64_t i = 0; i < nb; ++i) {
+        a.push_back((int32_t)(t.box_base + t.level_off[l] + i));
+        b.push_back(l > 0 ? (int32_t)(t.box_base + t.level_off[l - 1] + (i >> s)) : -1);
+      }
+    }
+    Step S;
+    S.n = (int64_t)a.size();
+    S.a = upload(a);
+    S.b = upload(b);
+    pl->l2l_steps.push_back(S);
+  }
+}
+
 namespace {
 
 int depth_for(int64_t n, int leaf, int s, int max_depth) {
@@ -129,6 +185,62 @@ void run_vectors(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void
   }
 }
 
+// Tree, geometry and lists of one point set (plan creation minus the
+// evaluation workspace).
+void build_structure(fmm_plan* pl, const double* pos, int64_t n, const fmm_params* prm,
+                     hipStream_t st) {
+  FMM_HIP(hipGetDevice(&pl->device));
+  pl->prm = *prm;
+  pl->n = n;
+  pl->s = prm->splits;
+  pl->nch = 1 << pl->s;
+  pl->L = depth_for(n, prm->leaf_max, pl->s, prm->max_depth);
+  pl->level_off.assign(pl->L + 2, 0);
+  for (int l = 0; l <= pl->L; ++l)
+    pl->level_off[l + 1] = pl->level_off[l] + ((int64_t)1 << (pl->s * l));
+  pl->nbox = pl->level_off[pl->L + 1];
+  pl->nleaf = (int64_t)1 << (pl->s * pl->L);
+  if (pl->nbox >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "too many boxes"};
+  pl->perm = (int32_t*)plan_alloc(pl, sizeof(int32_t) * n);
+  pl->leaf_start = (int32_t*)plan_alloc(pl, sizeof(int32_t) * (pl->nleaf + 1));
+  pl->xs = (double*)plan_alloc(pl, sizeof(double) * n);
+  pl->ys = (double*)plan_alloc(pl, sizeof(double) * n);
+  pl->zs = (double*)plan_alloc(pl, sizeof(double) * n);
+  pl->cx = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
+  pl->cy = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
+  pl->cz = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
+  pl->radius = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
+  pl->scale = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
+  build_tree(pl, pos, st);
+  build_lists(pl, st);
+}
+
+// Evaluation workspace sized from the plan's counts.
+void alloc_workspace(fmm_plan* pl, hipStream_t st) {
+  const fmm_params* prm = &pl->prm;
+  const int64_t n = pl->n;
+  const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+  const size_t K = (size_t)ncoef(prm->p);
+  const size_t ni =
+      (size_t)std::max<int64_t>(std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
+  pl->src = plan_alloc(pl, 32 * (size_t)n);
+  pl->C = plan_alloc(pl, es * K * (size_t)pl->nbox);
+  pl->D = plan_alloc(pl, es * K * (size_t)pl->nbox);
+  pl->partial = plan_alloc(pl, es * K * ni);
+  pl->field_t = plan_alloc(pl, es * 3 * (size_t)n);
+  if (prm->precision == FMM_FP32 && prm->max_rhs > 1) {
+    const size_t W = (size_t)batch_width() * sizeof(float);
+    pl->bq = plan_alloc(pl, W * n);
+    pl->bC = plan_alloc(pl, W * K * pl->nbox);
+    pl->bD = plan_alloc(pl, W * K * pl->nbox);
+    pl->bpart = plan_alloc(pl, W * K * ni);
+    pl->bpot = plan_alloc(pl, W * n);
+    pl->bfld = plan_alloc(pl, W * 3 * n);
+  }
+  pl->tables = get_tables(prm->p, prm->precision, pl->device);
+  FMM_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace
 }  // namespace fmm
 
@@ -149,56 +261,57 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
     try {
-      FMM_HIP(hipGetDevice(&pl->device));
-      pl->prm = *prm;
-      pl->n = n;
-      pl->s = prm->splits;
-      pl->nch = 1 << pl->s;
-      pl->L = depth_for(n, prm->leaf_max, pl->s, prm->max_depth);
-      pl->level_off.assign(pl->L + 2, 0);
-      for (int l = 0; l <= pl->L; ++l)
-        pl->level_off[l + 1] = pl->level_off[l] + ((int64_t)1 << (pl->s * l));
-      pl->nbox = pl->level_off[pl->L + 1];
-      pl->nleaf = (int64_t)1 << (pl->s * pl->L);
-      if (pl->nbox >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "too many boxes"};
-      pl->perm = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * n);
-      pl->leaf_start = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * (pl->nleaf + 1));
-      pl->xs = (double*)plan_alloc(pl.get(), sizeof(double) * n);
-      pl->ys = (double*)plan_alloc(pl.get(), sizeof(double) * n);
-      pl->zs = (double*)plan_alloc(pl.get(), sizeof(double) * n);
-      pl->cx = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
-      pl->cy = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
-      pl->cz = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
-      pl->radius = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
-      pl->scale = (double*)plan_alloc(pl.get(), sizeof(double) * pl->nbox);
-      pl->leaf_of = (int32_t*)plan_alloc(pl.get(), sizeof(int32_t) * n);
-      build_tree(pl.get(), pos, st);
-      build_lists(pl.get(), st);
-      const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
-      const size_t K = (size_t)ncoef(prm->p);
-      pl->src = plan_alloc(pl.get(), 32 * (size_t)n);
-      pl->C = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
-      pl->D = plan_alloc(pl.get(), es * K * (size_t)pl->nbox);
-      pl->partial = plan_alloc(
-          pl.get(), es * K *
-                        (size_t)std::max<int64_t>(
-                            std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1));
-      pl->field_t = plan_alloc(pl.get(), es * 3 * (size_t)n);
-      if (prm->precision == FMM_FP32 && prm->max_rhs > 1) {
-        const size_t W = (size_t)batch_width() * sizeof(float);
-        const size_t ni = (size_t)std::max<int64_t>(
-            std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
-        pl->bq = plan_alloc(pl.get(), W * n);
-        pl->bC = plan_alloc(pl.get(), W * K * pl->nbox);
-        pl->bD = plan_alloc(pl.get(), W * K * pl->nbox);
-        pl->bpart = plan_alloc(pl.get(), W * K * ni);
-        pl->bpot = plan_alloc(pl.get(), W * n);
-        pl->bfld = plan_alloc(pl.get(), W * 3 * n);
-      }
-      pl->tables = get_tables(prm->p, prm->precision, pl->device);
-      FMM_HIP(hipStreamSynchronize(st));
+      build_structure(pl.get(), pos, n, prm, st);
+      make_steps(pl.get(), {TreeDesc{pl->L, pl->level_off, 0}}, st);
+      alloc_workspace(pl.get(), st);
     } catch (...) {
       (void)hipStreamSynchronize(st);
+      plan_free_all(pl.get());
+      throw;
+    }
+    *out = pl.release();
+  });
+}
+
+fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int nprob,
+                                 const fmm_params* prm, void* stream, fmm_plan** out) {
+  return guard([&] {
+    if (!out) throw Error{FMM_EINVAL, "out is NULL"};
+    if (!pos || !offsets) throw Error{FMM_EINVAL, "pos and offsets must not be NULL"};
+    if (nprob < 1) throw Error{FMM_EINVAL, "nprob must be >= 1"};
+    if (offsets[0] != 0) throw Error{FMM_EINVAL, "offsets[0] must be 0"};
+    for (int k = 0; k < nprob; ++k)
+      if (offsets[k + 1] <= offsets[k])
+        throw Error{FMM_EINVAL, "every problem needs at least one point"};
+    check_params(prm, offsets[nprob]);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<std::unique_ptr<fmm_plan>> subs;
+    std::unique_ptr<fmm_plan> pl(new fmm_plan());
+    auto free_subs = [&] {
+      for (auto& u : subs) plan_free_all(u.get());
+      subs.clear();
+    };
+    try {
+      for (int k = 0; k < nprob; ++k) {
+        subs.emplace_back(new fmm_plan());
+        build_structure(subs.back().get(), pos + 3 * offsets[k], offsets[k + 1] - offsets[k], prm,
+                        st);
+      }
+      std::vector<const fmm_plan*> sp;
+      for (auto& u : subs) sp.push_back(u.get());
+      build_union(pl.get(), sp, st);
+      std::vector<TreeDesc> trees;
+      int64_t base = 0;
+      for (const fmm_plan* u : sp) {
+        trees.push_back(TreeDesc{u->L, u->level_off, base});
+        base += u->nbox;
+      }
+      make_steps(pl.get(), trees, st);
+      free_subs();
+      alloc_workspace(pl.get(), st);
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      free_subs();
       plan_free_all(pl.get());
       throw;
     }
@@ -369,6 +482,70 @@ fmm_status fmm_plan_read_profile(fmm_plan* pl, double* stage_ms, int64_t* passes
     for (int k = 0; k < FMM_NSTAGES; ++k) stage_ms[k] = acc[k];
     if (passes) *passes = (int64_t)pl->ev_rows.size();
     release_profile(pl);
+  });
+}
+
+fmm_status fmm_graph_create(fmm_plan* pl, int transposed, const void* q, int nrhs, void* pot,
+                            void* field, fmm_graph** out) {
+  return guard([&] {
+    if (!pl || !out) throw Error{FMM_EINVAL, "plan and out must not be NULL"};
+    if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
+    if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
+    check_device(pl);
+    std::unique_ptr<fmm_graph> g(new fmm_graph());
+    g->device = pl->device;
+    hipStream_t cs = nullptr;
+    FMM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool prof = pl->profiling;
+    pl->profiling = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        run_vectors(pl, transposed ? 1 : 0, q, nrhs, pot, field, cs);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        pl->profiling = prof;
+        throw;
+      }
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    pl->profiling = prof;
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      throw Error{FMM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e)};
+    }
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      throw Error{FMM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)};
+    }
+    *out = g.release();
+  });
+}
+
+fmm_status fmm_graph_launch(fmm_graph* g, void* stream) {
+  return guard([&] {
+    if (!g) throw Error{FMM_EINVAL, "graph is NULL"};
+    int dev = -1;
+    FMM_HIP(hipGetDevice(&dev));
+    if (dev != g->device) throw Error{FMM_EDEVICE, "current device differs from the graph's"};
+    FMM_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  });
+}
+
+fmm_status fmm_graph_destroy(fmm_graph* g) {
+  return guard([&] {
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
   });
 }
 

@@ -62,7 +62,7 @@ __global__ void k_bgather(int64_t n, int R, const int32_t* __restrict__ perm,
 
 template <int P>
 __global__ __launch_bounds__(64) void k_bp2m(
-    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
     const double* __restrict__ zs, const float* __restrict__ qL,
     const double* __restrict__ cx, const double* __restrict__ cy,
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64) void k_bp2m(
   const int lane = threadIdx.x;
   const int r = lane % kRB, h = lane / kRB;  // vector, half of the coefficients
   constexpr int KH = (K + 1) / 2;
-  const int64_t g = leaf_box0 + leaf;
+  const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   float acc[KH];
@@ -108,20 +108,21 @@ __global__ __launch_bounds__(64) void k_bp2m(
 // parent += M2M(child) over the 2^s children; one (parent, vector) per lane
 template <int P>
 __global__ __launch_bounds__(64) void k_bm2m(
-    int64_t npar, int64_t parent0, int64_t child0, int s, const double* __restrict__ cx,
+    int64_t npar, const int32_t* __restrict__ par, const int32_t* __restrict__ child0, int s,
+    const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ cz,
     const double* __restrict__ scale, const float* __restrict__ tab, float* C) {
   constexpr int K = K_<P>::value;
   const int64_t b = (int64_t)blockIdx.x * 2 + threadIdx.x / kRB;
   const int r = threadIdx.x % kRB;
   if (b >= npar) return;
-  const int64_t pa = parent0 + b;
+  const int64_t pa = par[b];
   float acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.f;
   const int nch = 1 << s;
   for (int c = 0; c < nch; ++c) {
-    const int64_t ch = child0 + b * nch + c;
+    const int64_t ch = child0[b] + c;
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = C[(ch * K + k) * kRB + r];
@@ -168,7 +169,8 @@ __global__ __launch_bounds__(64) void k_bm2l(
 
 template <int P>
 __global__ __launch_bounds__(64) void k_bl2l(
-    int64_t nb, int64_t box0, int64_t parent0, int s, const int32_t* __restrict__ item_ptr,
+    int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
+    const int32_t* __restrict__ item_ptr,
     const float* __restrict__ partial, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ cz,
     const double* __restrict__ scale, const float* __restrict__ tab, float* D) {
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(64) void k_bl2l(
   const int64_t i = (int64_t)blockIdx.x * 2 + threadIdx.x / kRB;
   const int r = threadIdx.x % kRB;
   if (i >= nb) return;
-  const int64_t t = box0 + i;
+  const int64_t t = boxes[i];
   float acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.f;
@@ -184,8 +186,8 @@ __global__ __launch_bounds__(64) void k_bl2l(
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += partial[((int64_t)it * K + k) * kRB + r];
   }
-  if (parent0 >= 0) {
-    const int64_t pa = parent0 + (i >> s);
+  const int64_t pa = parents[i];
+  if (pa >= 0) {
     float v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = D[(pa * K + k) * kRB + r];
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(64) void k_bl2l(
 // L2P for 32 points at a time: basis and gradient in LDS, lane r sums.
 template <int P>
 __global__ __launch_bounds__(64) void k_bl2p(
-    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
     const double* __restrict__ zs, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ cz,
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(64) void k_bl2p(
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
   const int r = lane % kRB, h = lane / kRB;
-  const int64_t g = leaf_box0 + leaf;
+  const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   const float fu = float(-kInv4Pi * ir), ff = float(kInv4Pi * ir * ir);
@@ -337,7 +339,7 @@ __global__ void k_bscatter(int64_t n, int R, const int32_t* __restrict__ perm,
 template <int P>
 void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* pot,
                float* field, hipStream_t st) {
-  const int L = pl->L, s = pl->s;
+  const int s = pl->s;
   const float* tab = (const float*)pl->tables;
   float* qL = (float*)pl->bq;
   float* C = (float*)pl->bC;
@@ -346,7 +348,6 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   float* potL = (float*)pl->bpot;
   float* fldL = (float*)pl->bfld;
   const int64_t n = pl->n;
-  const int64_t leaf0 = pl->level_off[L];
   std::vector<hipEvent_t>* row = nullptr;
   if (pl->profiling) {
     pl->ev_rows.emplace_back();
@@ -359,30 +360,26 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   mark(0);
   k_bgather<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, q, qL);
   mark(1);
-  k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs,
-                                                qL, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+  k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
+                                                pl->zs, qL, pl->cx, pl->cy, pl->cz, pl->scale,
+                                                tab, C);
   mark(2);
-  for (int l = L - 1; l >= 0; --l) {
-    const int64_t npar = pl->level_off[l + 1] - pl->level_off[l];
-    k_bm2m<P><<<blocks(npar, 2), 64, 0, st>>>(npar, pl->level_off[l], pl->level_off[l + 1], s,
-                                              pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
-  }
+  for (const Step& S : pl->m2m_steps)
+    k_bm2m<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
+                                             pl->scale, tab, C);
   mark(3);
   if (Ls.n_items > 0)
     k_bm2l<P><<<blocks(Ls.n_items, 2), 64, 0, st>>>(Ls.n_items, Ls.item_tgt, Ls.item_begin,
                                                     Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
                                                     pl->cz, pl->scale, C, tab, part);
   mark(4);
-  for (int l = 0; l <= L; ++l) {
-    const int64_t nb = pl->level_off[l + 1] - pl->level_off[l];
-    k_bl2l<P><<<blocks(nb, 2), 64, 0, st>>>(nb, pl->level_off[l],
-                                            l > 0 ? pl->level_off[l - 1] : -1, s, Ls.item_ptr,
-                                            part, pl->cx, pl->cy, pl->cz, pl->scale, tab, D);
-  }
+  for (const Step& S : pl->l2l_steps)
+    k_bl2l<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
+                                             pl->cz, pl->scale, tab, D);
   mark(5);
-  k_bl2p<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs,
-                                                pl->cx, pl->cy, pl->cz, pl->scale, D, tab, potL,
-                                                fldL);
+  k_bl2p<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
+                                                pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D,
+                                                tab, potL, fldL);
   mark(6);
   k_bp2p<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->xs, pl->ys, pl->zs, qL,
                                               Ls.p2p_ptr, Ls.p2p_src, potL, fldL);

@@ -48,7 +48,7 @@ constexpr int kM2LThreads = 64;
 // C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole)
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(
-    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
     const double* __restrict__ zs, const Src<T>* __restrict__ src,
     const double* __restrict__ cx, const double* __restrict__ cy,
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64) void k_p2m(
   __shared__ T red[K][65];
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t g = leaf_box0 + leaf;
+  const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   T acc[K];
 #pragma unroll
@@ -82,15 +82,16 @@ __global__ __launch_bounds__(64) void k_p2m(
 // ---------------------------------------------------------------- M2M
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_m2m(
-    int64_t nchild, int64_t child0, int64_t parent0, int s,
-    const double* __restrict__ cx, const double* __restrict__ cy,
+    int64_t nchild, const int32_t* __restrict__ par, const int32_t* __restrict__ child0,
+    int s, const double* __restrict__ cx, const double* __restrict__ cy,
     const double* __restrict__ cz, const double* __restrict__ scale,
     const T* __restrict__ tab, T* C) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < nchild;
-  const int64_t c = child0 + (live ? i : 0);
-  const int64_t pa = parent0 + ((live ? i : 0) >> s);
+  const int64_t ii = live ? i : 0;
+  const int64_t c = child0[ii >> s] + (ii & ((1 << s) - 1));
+  const int64_t pa = par[ii >> s];
   T v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = live ? C[c * K + k] : T(0);
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
 // D_t = (M2L partials of t, in item order) + L2L(D_parent)
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_l2l(
-    int64_t nb, int64_t box0, int64_t parent0, int s,
+    int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
     const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
     const double* __restrict__ cx, const double* __restrict__ cy,
     const double* __restrict__ cz, const double* __restrict__ scale,
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(64) void k_l2l(
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
-  const int64_t t = box0 + i;
+  const int64_t t = boxes[i];
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
@@ -159,8 +160,8 @@ __global__ __launch_bounds__(64) void k_l2l(
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += partial[(int64_t)it * K + k];
   }
-  if (parent0 >= 0) {
-    const int64_t pa = parent0 + (i >> s);
+  const int64_t pa = parents[i];
+  if (pa >= 0) {
     T v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(64) void k_l2l(
 // target leaf; writes (not adds) the outputs in input order.
 template <int P, typename T, bool FIELD>
 __global__ __launch_bounds__(64) void k_l2p(
-    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
+    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const int32_t* __restrict__ perm, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs,
     const double* __restrict__ cx, const double* __restrict__ cy,
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(64) void k_l2p(
   __shared__ T w[K];
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  const int64_t g = leaf_box0 + leaf;
+  const int64_t g = leaf_box[leaf];
   for (int k = lane; k < K; k += 64) w[k] = D[g * K + k] * tab[tab_l2p(P) + k];
   __syncthreads();
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
@@ -242,12 +243,9 @@ constexpr int kChunk = 8;
 // combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
-    int64_t leaf_box0, const int32_t* __restrict__ leaf_start,
-    const int32_t* __restrict__ perm, const Src<T>* __restrict__ src,
-    const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const double* __restrict__ scale,
-    const int32_t* __restrict__ p2p_ptr, const int32_t* __restrict__ p2p_src,
-    T* __restrict__ pot, T* __restrict__ field) {
+    const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
+    const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
+    const int32_t* __restrict__ p2p_src, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   const int leaf = blockIdx.x;
@@ -345,14 +343,13 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int P, typename T>
 void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStream_t st) {
-  const int L = pl->L, s = pl->s;
+  const int s = pl->s;
   const T* tab = (const T*)pl->tables;
   Src<T>* src = (Src<T>*)pl->src;
   T* C = (T*)pl->C;
   T* D = (T*)pl->D;
   T* part = (T*)pl->partial;
   const int64_t n = pl->n;
-  const int64_t leaf0 = pl->level_off[L];
   std::vector<hipEvent_t>* row = nullptr;
   if (pl->profiling) {
     pl->ev_rows.emplace_back();
@@ -365,13 +362,14 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mark(0);
   k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
   mark(1);
-  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs,
-                                                  src, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
+                                                  pl->zs, src, pl->cx, pl->cy, pl->cz, pl->scale,
+                                                  tab, C);
   mark(2);
-  for (int l = L - 1; l >= 0; --l) {
-    const int64_t nchild = pl->level_off[l + 2] - pl->level_off[l + 1];
-    k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, pl->level_off[l + 1], pl->level_off[l],
-                                                   s, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+  for (const Step& S : pl->m2m_steps) {
+    const int64_t nchild = S.n << s;
+    k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
+                                                   pl->scale, tab, C);
   }
   mark(3);
   if (Ls.n_items > 0)
@@ -379,27 +377,22 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
         Ls.n_items, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
         pl->cz, pl->scale, C, tab, part);
   mark(4);
-  for (int l = 0; l <= L; ++l) {
-    const int64_t nb = pl->level_off[l + 1] - pl->level_off[l];
-    k_l2l<P, T><<<blocks(nb, 64), 64, 0, st>>>(nb, pl->level_off[l],
-                                               l > 0 ? pl->level_off[l - 1] : -1, s,
-                                               Ls.item_ptr, part, pl->cx, pl->cy, pl->cz,
-                                               pl->scale, tab, D);
-  }
+  for (const Step& S : pl->l2l_steps)
+    k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
+                                                pl->cz, pl->scale, tab, D);
   mark(5);
   if (field)
     k_l2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
+        pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
         pl->scale, D, tab, pot, field);
   else
     k_l2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        leaf0, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
+        pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
         pl->scale, D, tab, pot, field);
   mark(6);
   const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
   auto p2p = [&](auto kern) {
-    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(leaf0, pl->leaf_start, pl->perm, src, pl->cx,
-                                              pl->cy, pl->cz, pl->scale, Ls.p2p_ptr,
+    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, Ls.p2p_ptr,
                                               Ls.p2p_src, pot, field);
   };
   if (field) {

@@ -61,6 +61,15 @@ struct ListSet {
   int64_t n_m2l = 0, n_p2p = 0, n_items = 0;
 };
 
+// One level step of the upward (M2M) or downward (L2L) pass: n boxes a[i]
+// with b[i] = first child (M2M; the 2^s children are consecutive) or parent
+// (L2L; -1 for a root).
+struct Step {
+  int32_t* a = nullptr;
+  int32_t* b = nullptr;
+  int64_t n = 0;
+};
+
 }  // namespace fmm
 
 struct fmm_plan {
@@ -82,8 +91,11 @@ struct fmm_plan {
   double* cz = nullptr;
   double* radius = nullptr;  // [nbox]
   double* scale = nullptr;   // [nbox] length scale of the box's expansions
-  int32_t* leaf_of = nullptr;  // [n] leaf of each leaf-ordered point
   int32_t max_leaf_count = 0;
+  int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
+  std::vector<fmm::Step> m2m_steps;  // bottom-up, parents of one level per step
+  std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level per step
+  int n_problems = 1;                // > 1: union of independent trees
 
   // lists (device): [0] forward, [1] transposed (every pair reversed; the
   // adjoint operator)
@@ -114,10 +126,31 @@ struct fmm_plan {
   std::vector<std::vector<hipEvent_t>> ev_rows;  // FMM_NSTAGES+1 per pass
 };
 
+// Captured evaluation (fmm_graph_create).
+struct fmm_graph {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace fmm {
 
 void* plan_alloc(fmm_plan* pl, size_t bytes);
 void plan_free_all(fmm_plan* pl);
+
+// One tree inside a plan: depth, level offsets and first global box id.
+struct TreeDesc {
+  int L;
+  std::vector<int64_t> level_off;
+  int64_t box_base;
+};
+// Leaf boxes and level steps over one or several trees (api.cpp).  M2M
+// step h takes the parents h+1 levels above each tree's leaves; L2L step l
+// takes level l of every tree at least that deep.
+void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st);
+// Union of independent plans (multi.hip): every per-point, per-box and
+// per-leaf array concatenated, indices shifted to global numbering.
+void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStream_t st);
 
 // Tree build (tree.hip): fills perm, leaf_start, xs/ys/zs, centres, radii.
 void build_tree(fmm_plan* pl, const double* pos, hipStream_t st);

@@ -148,12 +148,6 @@ __global__ void k_gather_pos(int n, const int32_t* __restrict__ perm,
   zs[j] = X[2 * (int64_t)n + i];
 }
 
-__global__ void k_leaf_of(int nleaf, const int32_t* __restrict__ leaf_start,
-                          int32_t* __restrict__ leaf_of) {
-  const int l = blockIdx.x;
-  for (int j = leaf_start[l] + threadIdx.x; j < leaf_start[l + 1]; j += blockDim.x) leaf_of[j] = l;
-}
-
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Temporary device memory released when the build ends.
@@ -270,7 +264,6 @@ void build_tree(fmm_plan* pl, const double* pos, hipStream_t st) {
                          st));
   k_gather_pos<<<blocks(n, T), T, 0, st>>>(n, lists[3], X, pl->xs, pl->ys,
                                            pl->zs);
-  k_leaf_of<<<(unsigned)nseg, 64, 0, st>>>(nseg, seg_start_d, pl->leaf_of);
   FMM_HIP(hipGetLastError());
   int mx = 0;
   for (int b = 0; b < nseg; ++b) mx = std::max(mx, seg[b + 1] - seg[b]);

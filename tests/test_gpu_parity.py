@@ -336,3 +336,141 @@ def test_batched_vectors_match_single_runs_and_oracle(fmm, kind, n, p, leaf, s, 
     Ut, _ = plan.evaluate_transposed(Qt)
     ut1, _ = single.evaluate_transposed(Qt[R - 1])
     assert _rel(Ut[R - 1].double().cpu().numpy(), ut1.double().cpu().numpy()) <= 1e-6
+
+
+MULTI_CASES = [
+    # precision, sizes, kinds, p, leaf, s, theta
+    ("fp64", [2500, 1, 7000, 300, 4100], ["cube", "cube", "cluster", "cube", "plummer"],
+     6, 64, 2, 0.6),
+    ("fp32", [5000, 1200, 40, 9000], ["cluster", "cube", "cube", "plummer"], 8, 128, 3, 0.7),
+]
+
+
+def _multi_inputs(sizes, kinds, seed):
+    ps, qs = [], []
+    for j, (n, k) in enumerate(zip(sizes, kinds)):
+        p_, q_ = _inputs(k, n, seed + j)
+        ps.append(p_)
+        qs.append(q_)
+    return ps, qs
+
+
+@pytest.mark.parametrize("prec,sizes,kinds,p,leaf,s,theta", MULTI_CASES)
+def test_multi_plan_matches_separate_plans_and_oracle(fmm, prec, sizes, kinds, p, leaf, s,
+                                                      theta):
+    """Several independent problems of different depths in one plan: tree
+    and lists are each problem's own (bit-identical to the oracle, indices
+    shifted), results equal separate plans and the oracle FMM."""
+    from oracle.fmm import fmm as oracle_fmm
+    from oracle.lists import build_lists
+    from oracle.tree import build_tree
+    _say(f"[multi] {prec} sizes={sizes} p={p} leaf={leaf} s={s} theta={theta}")
+    ps, qs = _multi_inputs(sizes, kinds, 40)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pos = torch.from_numpy(np.concatenate(ps)).cuda()
+    q = torch.from_numpy(np.concatenate(qs)).cuda().to(dt)
+    plan = fmm.Plan(pos, p=p, leaf_max=leaf, splits=s, theta=theta, precision=prec,
+                    sizes=sizes)
+    u, f = plan.evaluate(q)
+    ut, ft = plan.evaluate_transposed(q)
+    torch.cuda.synchronize()
+    perm, ls, c, r = plan.tree()
+    ms, mt, pps, ppt = plan.lists()
+    off = plan.offsets
+    pb = bb = lb = 0
+    m_all, p_all = [], []
+    tol_sep, tol_or = (1e-12, 1e-10) if prec == "fp64" else (1e-6, 1e-5)
+    for j, n in enumerate(sizes):
+        sl = slice(off[j], off[j + 1])
+        tr = build_tree(ps[j], leaf, s)
+        li = build_lists(tr, theta)
+        nb, nl = len(tr.radius), len(tr.leaf_start) - 1
+        assert np.array_equal(perm[sl], tr.perm + pb)
+        assert np.array_equal(ls[lb:lb + nl + 1], tr.leaf_start + pb)
+        assert np.array_equal(c[bb:bb + nb], tr.centre)
+        assert np.array_equal(r[bb:bb + nb], tr.radius)
+        m_all.append(np.stack([li.m2l_src + bb, li.m2l_tgt + bb]))
+        p_all.append(np.stack([li.p2p_src + lb, li.p2p_tgt + lb]))
+        sep = fmm.Plan(pos[sl], p=p, leaf_max=leaf, splits=s, theta=theta, precision=prec)
+        u1, f1 = sep.evaluate(q[sl])
+        ut1, _ = sep.evaluate_transposed(q[sl])
+        uj, fj = u[sl].double().cpu().numpy(), f[sl].double().cpu().numpy()
+        if n == 1:
+            assert np.all(uj == 0.0) and np.all(fj == 0.0)
+        else:
+            e_sep = max(_rel(uj, u1.double().cpu().numpy()), _rel(fj, f1.double().cpu().numpy()),
+                        _rel(ut[sl].double().cpu().numpy(), ut1.double().cpu().numpy()))
+            u0, f0 = oracle_fmm(ps[j], qs[j], p, leaf, s, theta)
+            e_or = max(_rel(uj, u0), _rel(fj, f0))
+            _say(f"    problem {j} n={n} depth {tr.L}: vs separate {e_sep:.2e} vs oracle {e_or:.2e}")
+            assert e_sep <= tol_sep and e_or <= tol_or
+        pb += n
+        bb += nb
+        lb += nl
+    m_all = np.concatenate(m_all, axis=1)
+    p_all = np.concatenate(p_all, axis=1)
+    o = np.lexsort((m_all[0], m_all[1]))
+    assert np.array_equal(ms, m_all[0][o]) and np.array_equal(mt, m_all[1][o])
+    o = np.lexsort((p_all[0], p_all[1]))
+    assert np.array_equal(pps, p_all[0][o]) and np.array_equal(ppt, p_all[1][o])
+
+
+def test_multi_plan_batched_vectors(fmm):
+    """Uneven problems and several charge vectors at once (FP32)."""
+    sizes = [6000, 500, 13000]
+    _say(f"[multi batched] sizes={sizes} R=6")
+    ps, _ = _multi_inputs(sizes, ["cube", "cluster", "plummer"], 60)
+    pos = torch.from_numpy(np.concatenate(ps)).cuda()
+    Q = torch.from_numpy(np.random.default_rng(61).uniform(-1, 1, (6, sum(sizes)))).cuda().float()
+    plan = fmm.Plan(pos, p=8, leaf_max=64, splits=2, theta=0.7, precision="fp32", max_rhs=6,
+                    sizes=sizes)
+    single = fmm.Plan(pos, p=8, leaf_max=64, splits=2, theta=0.7, precision="fp32",
+                      sizes=sizes)
+    U, Fd = plan.evaluate(Q)
+    worst = 0.0
+    for r in range(6):
+        u1, f1 = single.evaluate(Q[r])
+        worst = max(worst, _rel(U[r].double().cpu().numpy(), u1.double().cpu().numpy()),
+                    _rel(Fd[r].double().cpu().numpy(), f1.double().cpu().numpy()))
+    _say(f"    batched vs single: {worst:.2e}")
+    assert worst <= 1e-6
+
+
+GRAPH_CASES = [
+    # precision, sizes (None = one problem), n, R, transposed
+    ("fp64", None, 20000, 1, False),
+    ("fp64", None, 9000, 1, True),
+    ("fp32", [7000, 300, 12000, 1], None, 1, False),
+    ("fp32", [4000, 9000], None, 32, False),
+]
+
+
+@pytest.mark.parametrize("prec,sizes,n,R,transposed", GRAPH_CASES)
+def test_graph_replays_match_eager_runs(fmm, prec, sizes, n, R, transposed):
+    """A captured evaluation replayed several times, with new charges
+    written by ordinary eager work between replays, reproduces the eager
+    evaluation bit for bit on every replay."""
+    _say(f"[graph] {prec} sizes={sizes} n={n} R={R} transposed={transposed}")
+    if sizes is None:
+        pos, _ = workloads.uniform_cube(n, 70)
+        kw = {}
+    else:
+        pos = np.concatenate(_multi_inputs(sizes, ["cube", "cluster", "plummer", "cube"][:len(sizes)], 71)[0])
+        kw = {"sizes": sizes}
+    N = len(pos)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=6, leaf_max=64, splits=2, theta=0.6,
+                    precision=prec, max_rhs=R, **kw)
+    q = torch.empty((R, N), dtype=dt, device="cuda")
+    g = fmm.Graph(plan, q, field=True, transposed=transposed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(72)
+    for rep in range(4):
+        q.uniform_(-1, 1, generator=gen)
+        g.launch()
+        torch.cuda.synchronize()
+        ev = plan.evaluate_transposed if transposed else plan.evaluate
+        u, f = ev(q)
+        torch.cuda.synchronize()
+        _say(f"    replay {rep}")
+        assert torch.equal(g.pot, u) and torch.equal(g.field, f)

@@ -71,3 +71,33 @@ def test_null_arguments():
     assert lib.fmm_evaluate(None, None, 1, None, None, None) == L.FMM_EINVAL
     assert lib.fmm_plan_get_info(None, None) == L.FMM_EINVAL
     assert lib.fmm_plan_destroy(None) == L.FMM_OK
+
+
+@pytest.mark.parametrize("offsets,nprob", [
+    ([0], 0),                 # no problem
+    ([1, 10], 1),             # offsets[0] != 0
+    ([0, 10, 10], 2),         # an empty problem
+    ([0, 10, 5], 2),          # decreasing
+    ([0, 1 << 31], 1),        # total too large
+])
+def test_multi_plan_bad_offsets(offsets, nprob):
+    lib = L.lib()
+    prm = L.FmmParams(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16, precision=0,
+                      tie_refine=0, max_rhs=1)
+    off = (ctypes.c_int64 * len(offsets))(*offsets)
+    out = ctypes.c_void_p(777)
+    st = lib.fmm_multi_plan_create(ctypes.c_void_p(0x1000), off, nprob, ctypes.byref(prm), None,
+                                   ctypes.byref(out))
+    assert st == L.FMM_EINVAL
+    assert out.value == 777
+    assert lib.fmm_last_error().decode() != ""
+
+
+def test_graph_null_arguments():
+    lib = L.lib()
+    out = ctypes.c_void_p(5)
+    assert lib.fmm_graph_create(None, 0, None, 1, None, None, ctypes.byref(out)) == L.FMM_EINVAL
+    assert out.value == 5
+    assert lib.fmm_graph_launch(None, None) == L.FMM_EINVAL
+    assert lib.fmm_graph_destroy(None) == L.FMM_OK
+    assert lib.fmm_multi_plan_create(None, None, 1, None, None, ctypes.byref(out)) == L.FMM_EINVAL

@@ -33,6 +33,38 @@ __device__ __forceinline__ cptr<T> local_ptr(const T* p) {
   return (cptr<T>)p;
 }
 
+// Sequential reader of a constant table whose entries are consumed in
+// storage order at compile-time-known positions (fully unrolled loops).
+// Entries arrive through the scalar unit in 64-byte blocks, R blocks per
+// batch, double-buffered: right after the first use of batch j the loads
+// of batch j+1 are issued, so their latency overlaps the rest of batch j.
+// (Scalar loads may complete out of order, so a wait is always a wait for
+// every outstanding one; the first use of a batch comes before the next
+// batch is requested for that reason.)  Reads up to 2 R blocks past the
+// last entry used: the tables carry tab_pad() entries of padding.
+template <typename T>
+struct TabReader {
+  static constexpr int B = 64 / sizeof(T);  // entries per block
+  static constexpr int R = 2;               // blocks per batch
+  static constexpr int BR = B * R;
+  cptr<T> p;
+  T buf[2][BR];
+  __device__ __forceinline__ explicit TabReader(cptr<T> q) : p(q) { fetch(0); }
+  __device__ __forceinline__ void fetch(int batch) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i) buf[batch & 1][i] = p[batch * BR + i];
+  }
+  __device__ __forceinline__ T get(int o) const { return buf[(o / BR) & 1][o % BR]; }
+  // call after the use of entry o
+  __device__ __forceinline__ void used(int o) {
+    if (o % BR == 0) {
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(o / BR + 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+};
+
 // cos(m g), sin(m g), m = 0..P, by repeated complex multiplication
 template <int P, typename T>
 __device__ __forceinline__ void powers(T c1, T s1, T* c, T* s) {
@@ -75,24 +107,32 @@ __device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
   }
 }
 
-// v_n <- Y_n v_n (TR: Y_n^T v_n) over the stored nonzero entries
+// v_n <- Y_n v_n (TR: Y_n^T v_n) over the nonzero entries, column by
+// column: each input coefficient is scattered into the output rows it
+// reaches, so consecutive multiply-adds go to different accumulators.  The
+// column-major order of Y_n is the row-major order of Y_n^T, so the product
+// with Y_n reads the stored Y_n^T rows and vice versa.
 template <int P, bool TR, typename T>
 __device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
+  TabReader<T> Y(local_ptr(tab) + (TR ? tab_y(P) : tab_yt(P)) + ycbase(1));
+  int o = 0;
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
-    cptr<T> Y = local_ptr(tab) + (TR ? tab_yt(P) : tab_y(P)) + ycbase(n);
     T u[2 * P + 1];
-    int o = 0;
+    bool live[2 * P + 1];
 #pragma unroll
-    for (int a = -n; a <= n; ++a) {
-      T acc = T(0);
+    for (int a = 0; a <= 2 * n; ++a) live[a] = false;
 #pragma unroll
-      for (int b = -n; b <= n; ++b) {
+    for (int b = -n; b <= n; ++b) {
+      const T vb = v[cidx(n, b)];
+#pragma unroll
+      for (int a = -n; a <= n; ++a) {
         if (!ynz(n, a, b)) continue;
-        acc = fma(Y[o], v[cidx(n, b)], acc);
+        u[a + n] = live[a + n] ? fma(Y.get(o), vb, u[a + n]) : Y.get(o) * vb;
+        live[a + n] = true;
+        Y.used(o);
         ++o;
       }
-      u[a + n] = acc;
     }
 #pragma unroll
     for (int a = -n; a <= n; ++a) v[cidx(n, a)] = u[a + n];
@@ -120,21 +160,26 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
     for (int n = 0; n <= P; ++n)
 #pragma unroll
       for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pa[n];
+    // table column by column (k outer): independent accumulators; the
+    // blocks of -m and +m are the same, read twice in a row
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
-      cptr<T> tb = local_ptr(tab) + tab_tm2l(P) + zl_base(P, am);
+      TabReader<T> tb(local_ptr(tab) + tab_tm2l(P) + zl_base(P, am));
       T o[P + 1];
       int c = 0;
 #pragma unroll
-      for (int n = am; n <= P; ++n) {
-        T acc = T(0);
+      for (int k = am; k <= P; ++k) {
+        const T vk = v[cidx(k, m)];
 #pragma unroll
-        for (int k = am; k <= P; ++k) acc = fma(tb[c++], v[cidx(k, m)], acc);
-        o[n] = acc * pb[n + 1];
+        for (int n = am; n <= P; ++n) {
+          o[n] = k == am ? tb.get(c) * vk : fma(tb.get(c), vk, o[n]);
+          tb.used(c);
+          ++c;
+        }
       }
 #pragma unroll
-      for (int n = am; n <= P; ++n) v[cidx(n, m)] = m < 0 ? -o[n] : o[n];
+      for (int n = am; n <= P; ++n) v[cidx(n, m)] = m < 0 ? -(o[n] * pb[n + 1]) : o[n] * pb[n + 1];
     }
   } else {
     if (KIND == kM2M) {
@@ -146,7 +191,8 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
-      cptr<T> tb = local_ptr(tab) + (KIND == kM2M ? tab_tm2m(P) : tab_tl2l(P)) + zt_base(P, am);
+      TabReader<T> tb(local_ptr(tab) + (KIND == kM2M ? tab_tm2m(P) : tab_tl2l(P)) +
+                      zt_base(P, am));
       T o[P + 1];
       int c = 0;
 #pragma unroll
@@ -154,10 +200,16 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
         T acc = T(0);
         if (KIND == kM2M) {
 #pragma unroll
-          for (int k = am; k <= n; ++k) acc = fma(tb[c++] * pa[n - k], v[cidx(k, m)], acc);
+          for (int k = am; k <= n; ++k) {
+            acc = fma(tb.get(c) * pa[n - k], v[cidx(k, m)], acc);
+            tb.used(c++);
+          }
         } else {
 #pragma unroll
-          for (int k = n; k <= P; ++k) acc = fma(tb[c++] * pa[k - n], v[cidx(k, m)], acc);
+          for (int k = n; k <= P; ++k) {
+            acc = fma(tb.get(c) * pa[k - n], v[cidx(k, m)], acc);
+            tb.used(c++);
+          }
           acc *= pb[n + 1];
         }
         o[n] = acc;

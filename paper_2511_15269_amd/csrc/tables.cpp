@@ -92,7 +92,7 @@ std::vector<double> wigner_d(int P, double beta) {
 }
 
 std::vector<double> build(int P) {
-  std::vector<double> t((size_t)tab_size(P), 0.0);
+  std::vector<double> t((size_t)(tab_size(P) + tab_pad()), 0.0);
   const double s2 = std::sqrt(2.0);
   for (int n = 0; n <= P; ++n)
     for (int m = -n; m <= n; ++m) {
@@ -129,8 +129,8 @@ std::vector<double> build(int P) {
   }
   for (int am = 0; am <= P; ++am) {
     int o = tab_tm2l(P) + zl_base(P, am);
-    for (int n = am; n <= P; ++n)
-      for (int k = am; k <= P; ++k)
+    for (int k = am; k <= P; ++k)  // column-major: read k by k
+      for (int n = am; n <= P; ++n)
         t[o++] = (((k + am) % 2) ? -1.0 : 1.0) * fact(n + k) / (Nnm(n, am) * Nnm(k, am));
     o = tab_tm2m(P) + zt_base(P, am);
     for (int n = am; n <= P; ++n)

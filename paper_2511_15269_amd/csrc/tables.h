@@ -32,7 +32,8 @@ FMM_HD int ycbase(int n) {  // sum_{j<n} ycount(j)
   return (n - 1) * n * (n + 1) / 3 + n;
 }
 // z-axis translation coefficients per |m|, n, k (App. B.3, normalised):
-// M2L has n, k in [|m|, P]; M2M k in [|m|, n]; L2L k in [n, P].
+// M2L has n, k in [|m|, P] (stored column by column, k outer); M2M k in
+// [|m|, n] and L2L k in [n, P] (row by row, n outer).
 FMM_HD int zl_base(int P, int am) {  // sum_{j<am} (P+1-j)^2
   int s = 0;
   for (int j = 0; j < am; ++j) s += (P + 1 - j) * (P + 1 - j);
@@ -55,5 +56,8 @@ FMM_HD int tab_tm2l(int P) { return tab_yt(P) + ycbase(P + 1); }
 FMM_HD int tab_tm2m(int P) { return tab_tm2l(P) + zl_base(P, P + 1); }
 FMM_HD int tab_tl2l(int P) { return tab_tm2m(P) + zt_base(P, P + 1); }
 FMM_HD int tab_size(int P) { return tab_tl2l(P) + zt_base(P, P + 1); }
+// Zero entries after the last table: kernels prefetch whole 64-byte blocks
+// ahead of use and may read up to this many entries past the end.
+FMM_HD int tab_pad() { return 64; }
 
 }  // namespace fmm

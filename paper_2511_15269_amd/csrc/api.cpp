@@ -73,6 +73,31 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
   pl->leaf_box = upload(lb);
   pl->m2m_steps.clear();
   pl->l2l_steps.clear();
+  // Boxes whose expansions matter: those in an M2L pair (either role, so
+  // both the forward and the transposed pass are covered) and all their
+  // descendants.  Multipoles of other boxes are never read; locals of other
+  // non-leaf boxes are zero and are not formed (children skip the
+  // translation from them).
+  std::vector<char> active(pl->nbox, 0);
+  {
+    const ListSet& F = pl->lists[0];
+    std::vector<int32_t> ptr(pl->nbox + 1), src(std::max<int64_t>(F.n_m2l, 1));
+    FMM_HIP(hipMemcpyAsync(ptr.data(), F.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
+                           hipMemcpyDeviceToHost, st));
+    if (F.n_m2l > 0)
+      FMM_HIP(hipMemcpyAsync(src.data(), F.m2l_src, sizeof(int32_t) * F.n_m2l,
+                             hipMemcpyDeviceToHost, st));
+    FMM_HIP(hipStreamSynchronize(st));
+    for (int64_t b = 0; b < pl->nbox; ++b)
+      if (ptr[b + 1] > ptr[b]) active[b] = 1;
+    for (int64_t k = 0; k < F.n_m2l; ++k) active[src[k]] = 1;
+    for (const TreeDesc& t : trees)
+      for (int l = 1; l <= t.L; ++l)
+        for (int64_t i = 0; i < t.level_off[l + 1] - t.level_off[l]; ++i) {
+          const int64_t b = t.box_base + t.level_off[l] + i;
+          if (active[t.box_base + t.level_off[l - 1] + (i >> s)]) active[b] = 1;
+        }
+  }
   // Upward: step h takes the parents h+1 levels above each tree's leaves.
   for (int h = 0; h < Lmax; ++h) {
     std::vector<int32_t> a, b;
@@ -81,10 +106,13 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
       if (l < 0) continue;
       const int64_t np = t.level_off[l + 1] - t.level_off[l];
       for (int64_t i = 0; i < np; ++i) {
-        a.push_back((int32_t)(t.box_base + t.level_off[l] + i));
+        const int64_t p = t.box_base + t.level_off[l] + i;
+        if (!active[p]) continue;
+        a.push_back((int32_t)p);
         b.push_back((int32_t)(t.box_base + t.level_off[l + 1] + (i << s)));
       }
     }
+    if (a.empty()) continue;
     Step S;
     S.n = (int64_t)a.size();
     S.a = upload(a);
@@ -98,10 +126,14 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
       if (l > t.L) continue;
       const int64_t nb = t.level_off[l + 1] - t.level_off[l];
       for (int64_t i = 0; i < nb; ++i) {
-        a.push_back((int32_t)(t.box_base + t.level_off[l] + i));
-        b.push_back(l > 0 ? (int32_t)(t.box_base + t.level_off[l - 1] + (i >> s)) : -1);
+        const int64_t bx = t.box_base + t.level_off[l] + i;
+        if (!active[bx] && l < t.L) continue;  // leaves are always written
+        const int64_t pa = l > 0 ? t.box_base + t.level_off[l - 1] + (i >> s) : -1;
+        a.push_back((int32_t)bx);
+        b.push_back(pa >= 0 && active[pa] ? (int32_t)pa : -1);
       }
     }
+    if (a.empty()) continue;
     Step S;
     S.n = (int64_t)a.size();
     S.a = upload(a);

@@ -45,37 +45,58 @@ using namespace ops;
 constexpr int kM2LThreads = 64;
 
 // ---------------------------------------------------------------- P2M
-// C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole)
-template <int P, typename T>
+// C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole).
+// G leaves per wave (LW = 64/G lanes each, lane = point); the per-lane sums
+// are combined by a butterfly over the leaf's lanes.
+template <int P, typename T, int G>
 __global__ __launch_bounds__(64) void k_p2m(
-    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
-    const double* __restrict__ xs, const double* __restrict__ ys,
-    const double* __restrict__ zs, const Src<T>* __restrict__ src,
-    const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const double* __restrict__ scale,
-    const T* __restrict__ tab, T* __restrict__ C) {
+    int64_t nleaf, const int32_t* __restrict__ leaf_box,
+    const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const Src<T>* __restrict__ src, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const double* __restrict__ scale, const T* __restrict__ tab, T* __restrict__ C) {
   constexpr int K = K_<P>::value;
-  __shared__ T red[K][65];
-  const int leaf = blockIdx.x;
+  constexpr int LW = 64 / G;
+  __shared__ T cs[G][K];  // finished sums, stored coalesced at the end
   const int lane = threadIdx.x;
-  const int64_t g = leaf_box[leaf];
-  const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
-  T acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  const int h = lane / LW, l = lane % LW;
+  const int64_t leaf = (int64_t)blockIdx.x * G + h;
+  const bool has = leaf < nleaf;
+  const int64_t g = has ? leaf_box[leaf] : 0;
+  const int st = has ? leaf_start[leaf] : 0, en = has ? leaf_start[leaf + 1] : 0;
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
-  for (int j = st + lane; j < en; j += 64) {
-    const T qj = src[j].q;
-    regular_basis<P, T>(T((xs[j] - ox) * ir), T((ys[j] - oy) * ir), T((zs[j] - oz) * ir),
-                        [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
-  }
+  if (G > 1) {
+    // at most one point per lane: reduce every coefficient as it is formed
+    const int j = st + l;
+    const bool pt = j < en;
+    const T qj = pt ? src[j].q : T(0);
+    const int jj = pt ? j : st;
+    regular_basis<P, T>(T((xs[jj] - ox) * ir), T((ys[jj] - oy) * ir), T((zs[jj] - oz) * ir),
+                        [&](int k, T v) {
+                          const T sum = group_sum<LW>(qj * v);
+                          if (l == LW - 1) cs[h][k] = sum;
+                        });
+  } else {
+    T acc[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) red[k][lane] = acc[k];
+    for (int k = 0; k < K; ++k) acc[k] = T(0);
+    for (int j = st + l; j < en; j += LW) {
+      const T qj = src[j].q;
+      regular_basis<P, T>(T((xs[j] - ox) * ir), T((ys[j] - oy) * ir), T((zs[j] - oz) * ir),
+                          [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const T sum = group_sum<LW>(acc[k]);
+      if (l == LW - 1) cs[0][k] = sum;
+    }
+  }
   __syncthreads();
-  for (int k = lane; k < K; k += 64) {
-    T s = T(0);
-    for (int l = 0; l < 64; ++l) s += red[k][l];
-    C[g * K + k] = s * tab[tab_normc(P) + k];
+  for (int idx = lane; idx < G * K; idx += 64) {
+    const int hh = idx / K, k = idx - hh * K;
+    const int64_t lf = (int64_t)blockIdx.x * G + hh;
+    if (lf < nleaf) C[(int64_t)leaf_box[lf] * K + k] = cs[hh][k] * tab[tab_normc(P) + k];
   }
 }
 
@@ -177,30 +198,38 @@ __global__ __launch_bounds__(64) void k_l2l(
 // ---------------------------------------------------------------- L2P
 // L2P: u = -1/(4 pi) (1/rho) sum w_m D R-hat(y), y = (x - c)/rho, and
 // field = -grad u (an extra 1/rho from the chain rule), at every point of the
-// target leaf; writes (not adds) the outputs in input order.
-template <int P, typename T, bool FIELD>
+// target leaf; writes (not adds) the outputs in input order.  G leaves per
+// wave, LW = 64/G lanes each, lane = point.
+template <int P, typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_l2p(
-    const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
-    const int32_t* __restrict__ perm, const double* __restrict__ xs,
-    const double* __restrict__ ys, const double* __restrict__ zs,
-    const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const double* __restrict__ scale,
-    const T* __restrict__ D, const T* __restrict__ tab, T* __restrict__ pot,
-    T* __restrict__ field) {
+    int64_t nleaf, const int32_t* __restrict__ leaf_box,
+    const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
+    const double* __restrict__ xs, const double* __restrict__ ys,
+    const double* __restrict__ zs, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const double* __restrict__ scale, const T* __restrict__ D, const T* __restrict__ tab,
+    T* __restrict__ pot, T* __restrict__ field) {
   constexpr int K = K_<P>::value;
-  __shared__ T w[K];
-  const int leaf = blockIdx.x;
+  constexpr int LW = 64 / G;
+  __shared__ T w[G][K];
   const int lane = threadIdx.x;
-  const int64_t g = leaf_box[leaf];
-  for (int k = lane; k < K; k += 64) w[k] = D[g * K + k] * tab[tab_l2p(P) + k];
+  const int h = lane / LW, l = lane % LW;
+  for (int idx = lane; idx < G * K; idx += 64) {
+    const int hh = idx / K, k = idx - hh * K;
+    const int64_t lf = (int64_t)blockIdx.x * G + hh;
+    if (lf < nleaf) w[hh][k] = D[(int64_t)leaf_box[lf] * K + k] * tab[tab_l2p(P) + k];
+  }
   __syncthreads();
+  const int64_t leaf = (int64_t)blockIdx.x * G + h;
+  if (leaf >= nleaf) return;
+  const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   const T fu = T(-kInv4Pi * ir), ff = T(kInv4Pi * ir * ir);
-  for (int i = st + lane; i < en; i += 64) {
+  for (int i = st + l; i < en; i += LW) {
     T fp = T(0), fx = T(0), fy = T(0), fz = T(0);
-    local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w, fp,
-                     fx, fy, fz);
+    local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w[h],
+                     fp, fx, fy, fz);
     const int o = perm[i];
     pot[o] = fu * fp;
     if (FIELD) {
@@ -237,8 +266,11 @@ constexpr int kChunk = 8;
 // Block = target leaf, lane = target point.  G source groups: lanes
 // [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
 // G-th source point starting at point g.  G = 1 keeps all source reads
-// wave-uniform (scalar loads); G = 2, 4 fill the wave when leaves hold at
-// most 32 or 16 points.  Per source leaf the partial sums are added to the
+// wave-uniform (scalar loads).  G = 2, 4 fill the wave when leaves hold at
+// most 32 or 16 points; each source leaf is then first copied into LDS with
+// one coalesced 16-byte load per lane, and the groups read their records
+// from there (a per-lane global read of every record would saturate the
+// texture address unit).  Per source leaf the partial sums are added to the
 // running sums with Neumaier compensation (FP32 form); group sums are then
 // combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
@@ -248,6 +280,8 @@ __global__ __launch_bounds__(64) void k_p2p(
     const int32_t* __restrict__ p2p_src, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
+  // G > 1: one source leaf (at most TL points) staged as 16-byte words
+  __shared__ __align__(32) double2 stage[G > 1 ? 2 * TL : 1];
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
   const int g = G == 1 ? 0 : lane / TL;
@@ -264,18 +298,35 @@ __global__ __launch_bounds__(64) void k_p2p(
       const int js = leaf_start[sl], cnt = leaf_start[sl + 1] - js;
       T lu = T(0), lx = T(0), ly = T(0), lz = T(0);
       const int full = cnt / G;  // points per group present in every group
-      const Src<T>* base = src + js + g;
-      int c = 0;
-      for (; c + kChunk <= full; c += kChunk) {
-        Src<T> r[kChunk];
+      if (G == 1) {
+        const Src<T>* base = src + js;
+        int c = 0;
+        for (; c + kChunk <= full; c += kChunk) {
+          Src<T> r[kChunk];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) r[t] = base[(c + t) * G];
+          for (int t = 0; t < kChunk; ++t) r[t] = base[c + t];
 #pragma unroll
-        for (int t = 0; t < kChunk; ++t) p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, lu, lx, ly, lz);
+          for (int t = 0; t < kChunk; ++t)
+            p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, lu, lx, ly, lz);
+        }
+        for (; c < full; ++c) p2p_pair<T, FIELD>(base[c], a.x, a.y, a.z, lu, lx, ly, lz);
+      } else {
+        // cnt <= TL: the leaf's records are 2 cnt <= 64 words
+        const double2* words = reinterpret_cast<const double2*>(src + js);
+        __syncthreads();  // previous leaf's reads are done
+        if (lane < 2 * cnt) stage[lane] = words[lane];
+        __syncthreads();
+        const Src<T>* rec = reinterpret_cast<const Src<T>*>(stage) + g;
+        int c = 0;
+        for (; c + kChunk <= full; c += kChunk) {
+#pragma unroll
+          for (int t = 0; t < kChunk; ++t)
+            p2p_pair<T, FIELD>(rec[(c + t) * G], a.x, a.y, a.z, lu, lx, ly, lz);
+        }
+        for (; c < full; ++c) p2p_pair<T, FIELD>(rec[c * G], a.x, a.y, a.z, lu, lx, ly, lz);
+        if (g < cnt - full * G)
+          p2p_pair<T, FIELD>(rec[full * G], a.x, a.y, a.z, lu, lx, ly, lz);
       }
-      for (; c < full; ++c) p2p_pair<T, FIELD>(base[c * G], a.x, a.y, a.z, lu, lx, ly, lz);
-      if (G > 1 && g < cnt - full * G)
-        p2p_pair<T, FIELD>(base[full * G], a.x, a.y, a.z, lu, lx, ly, lz);
       if (kComp) {
         neumaier(u, cu, lu);
         if (FIELD) {
@@ -362,9 +413,19 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mark(0);
   k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
   mark(1);
-  k_p2m<P, T><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
-                                                  pl->zs, src, pl->cx, pl->cy, pl->cz, pl->scale,
-                                                  tab, C);
+  // leaves per wave for P2M and L2P: every lane holds at most one point
+  const int mlc = pl->max_leaf_count;
+  const int GL = mlc > 32 ? 1 : (mlc > 16 ? 2 : (mlc > 8 ? 4 : 8));
+  const int64_t nl = pl->nleaf;
+  const unsigned nb_l = (unsigned)((nl + GL - 1) / GL);
+  auto p2m = [&](auto kern) {
+    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs, src,
+                              pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+  };
+  if (GL == 1) p2m(k_p2m<P, T, 1>);
+  else if (GL == 2) p2m(k_p2m<P, T, 2>);
+  else if (GL == 4) p2m(k_p2m<P, T, 4>);
+  else p2m(k_p2m<P, T, 8>);
   mark(2);
   for (const Step& S : pl->m2m_steps) {
     const int64_t nchild = S.n << s;
@@ -381,14 +442,21 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
     k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
                                                 pl->cz, pl->scale, tab, D);
   mark(5);
-  if (field)
-    k_l2p<P, T, true><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
-        pl->scale, D, tab, pot, field);
-  else
-    k_l2p<P, T, false><<<(unsigned)pl->nleaf, 64, 0, st>>>(
-        pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys, pl->zs, pl->cx, pl->cy, pl->cz,
-        pl->scale, D, tab, pot, field);
+  auto l2p = [&](auto kern) {
+    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys,
+                              pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, pot, field);
+  };
+  if (field) {
+    if (GL == 1) l2p(k_l2p<P, T, true, 1>);
+    else if (GL == 2) l2p(k_l2p<P, T, true, 2>);
+    else if (GL == 4) l2p(k_l2p<P, T, true, 4>);
+    else l2p(k_l2p<P, T, true, 8>);
+  } else {
+    if (GL == 1) l2p(k_l2p<P, T, false, 1>);
+    else if (GL == 2) l2p(k_l2p<P, T, false, 2>);
+    else if (GL == 4) l2p(k_l2p<P, T, false, 4>);
+    else l2p(k_l2p<P, T, false, 8>);
+  }
   mark(6);
   const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
   auto p2p = [&](auto kern) {

@@ -146,7 +146,9 @@ struct TreeDesc {
 };
 // Leaf boxes and level steps over one or several trees (api.cpp).  M2M
 // step h takes the parents h+1 levels above each tree's leaves; L2L step l
-// takes level l of every tree at least that deep.
+// takes level l of every tree at least that deep.  Boxes outside every M2L
+// pair and without such an ancestor are left out (their expansions are
+// never read, or are zero), except that every leaf gets its local.
 void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st);
 // Union of independent plans (multi.hip): every per-point, per-box and
 // per-leaf array concatenated, indices shifted to global numbering.

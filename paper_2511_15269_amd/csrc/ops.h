@@ -358,6 +358,8 @@ __device__ __forceinline__ void basis_with_gradient(T x, T y, T z, F&& f) {
       const T nsy = (x * ssy - y * scy - sc) * fm;
       sc = nc; ss = ns; scx = ncx; scy = ncy; ssx = nsx; ssy = nsy;
     }
+    // keep each order's reads of the callback's operands inside its band
+    __builtin_amdgcn_sched_barrier(0);
     f(cidx(m, m), sc, scx, scy, T(0));
     if (m > 0) f(cidx(m, -m), ss, ssx, ssy, T(0));
     // previous two degrees for +m (c) and -m (s): value, gradient
@@ -413,6 +415,35 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
   return y * fma(-0.5 * r2, y * y, 1.5);
 }
 __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+// ------------------------------------------------------ lane reductions
+// Cross-lane moves through the VALU's data-parallel primitives (no LDS).
+// CTRL: quad_perm / row_mirror / row_bcast selector; RM: rows written (the
+// others receive 0).
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, 0xF, false));
+}
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RM, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each aligned group of LW lanes (LW a power of two <= 64), in a
+// fixed order; the result is valid in the last lane of every group.
+template <int LW, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if (LW >= 2) v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]: lane ^ 1
+  if (LW >= 4) v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]: lane ^ 2
+  if (LW >= 8) v += dpp<0x141>(v);       // row_half_mirror: other quad of 8
+  if (LW >= 16) v += dpp<0x140>(v);      // row_mirror: other half of 16
+  if (LW >= 32) v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  if (LW >= 64) v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
 
 // Neumaier's compensated addition: s + c carries the running sum.
 template <typename T>

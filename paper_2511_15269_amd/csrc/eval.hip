@@ -34,6 +34,8 @@
 //             wave-uniform (scalar) loads.
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "ops.h"
 #include "tables.h"
@@ -241,15 +243,16 @@ __global__ __launch_bounds__(64) void k_l2p(
 }
 
 // One source point against the lane's target at (xi, yi, zi): the
-// difference is taken in FP64 and rounded to T; pairs at distance 0
-// contribute nothing.
-template <typename T, bool FIELD>
+// difference is taken in FP64 and rounded to T.  SAFE: pairs at distance 0
+// contribute nothing (needed within a leaf, and between leaves when the
+// point set has coincident points); otherwise the pair is known to be apart.
+template <typename T, bool FIELD, bool SAFE>
 __device__ __forceinline__ void p2p_pair(const Src<T>& s, double xi, double yi, double zi,
                                          T& u, T& gx, T& gy, T& gz) {
   const T dx = T(xi - s.x), dy = T(yi - s.y), dz = T(zi - s.z);
   const T r2 = dx * dx + dy * dy + dz * dz;
   const T inv0 = inv_sqrt(r2);
-  const T inv = r2 > T(0) ? inv0 : T(0);
+  const T inv = SAFE ? (r2 > T(0) ? inv0 : T(0)) : inv0;
   const T qi = s.q * inv;
   u += qi;
   if (FIELD) {
@@ -277,7 +280,7 @@ template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
     const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
     const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
-    const int32_t* __restrict__ p2p_src, T* __restrict__ pot, T* __restrict__ field) {
+    const int32_t* __restrict__ p2p_src, int dup, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   // G > 1: one source leaf (at most TL points) staged as 16-byte words
@@ -298,35 +301,42 @@ __global__ __launch_bounds__(64) void k_p2p(
       const int js = leaf_start[sl], cnt = leaf_start[sl + 1] - js;
       T lu = T(0), lx = T(0), ly = T(0), lz = T(0);
       const int full = cnt / G;  // points per group present in every group
+      // distance-0 guard only where it can matter: the target leaf itself,
+      // or every leaf when the point set has coincident points
+      const bool safe = dup || sl == leaf;
+      const Src<T>* rec;
+      int stride;
       if (G == 1) {
-        const Src<T>* base = src + js;
-        int c = 0;
-        for (; c + kChunk <= full; c += kChunk) {
-          Src<T> r[kChunk];
-#pragma unroll
-          for (int t = 0; t < kChunk; ++t) r[t] = base[c + t];
-#pragma unroll
-          for (int t = 0; t < kChunk; ++t)
-            p2p_pair<T, FIELD>(r[t], a.x, a.y, a.z, lu, lx, ly, lz);
-        }
-        for (; c < full; ++c) p2p_pair<T, FIELD>(base[c], a.x, a.y, a.z, lu, lx, ly, lz);
+        rec = src + js;
+        stride = 1;
       } else {
         // cnt <= TL: the leaf's records are 2 cnt <= 64 words
         const double2* words = reinterpret_cast<const double2*>(src + js);
         __syncthreads();  // previous leaf's reads are done
         if (lane < 2 * cnt) stage[lane] = words[lane];
         __syncthreads();
-        const Src<T>* rec = reinterpret_cast<const Src<T>*>(stage) + g;
+        rec = reinterpret_cast<const Src<T>*>(stage) + g;
+        stride = G;
+      }
+      auto sweep = [&](auto safe_tag) {
+        constexpr bool S = decltype(safe_tag)::value;
         int c = 0;
         for (; c + kChunk <= full; c += kChunk) {
+          Src<T> r[kChunk];
+#pragma unroll
+          for (int t = 0; t < kChunk; ++t) r[t] = rec[(c + t) * stride];
 #pragma unroll
           for (int t = 0; t < kChunk; ++t)
-            p2p_pair<T, FIELD>(rec[(c + t) * G], a.x, a.y, a.z, lu, lx, ly, lz);
+            p2p_pair<T, FIELD, S>(r[t], a.x, a.y, a.z, lu, lx, ly, lz);
         }
-        for (; c < full; ++c) p2p_pair<T, FIELD>(rec[c * G], a.x, a.y, a.z, lu, lx, ly, lz);
-        if (g < cnt - full * G)
-          p2p_pair<T, FIELD>(rec[full * G], a.x, a.y, a.z, lu, lx, ly, lz);
-      }
+        for (; c < full; ++c) p2p_pair<T, FIELD, S>(rec[c * stride], a.x, a.y, a.z, lu, lx, ly, lz);
+        if (G > 1 && g < cnt - full * G)
+          p2p_pair<T, FIELD, S>(rec[full * G], a.x, a.y, a.z, lu, lx, ly, lz);
+      };
+      if (safe)
+        sweep(std::true_type{});
+      else
+        sweep(std::false_type{});
       if (kComp) {
         neumaier(u, cu, lu);
         if (FIELD) {
@@ -461,7 +471,7 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
   auto p2p = [&](auto kern) {
     kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, Ls.p2p_ptr,
-                                              Ls.p2p_src, pot, field);
+                                              Ls.p2p_src, pl->has_dup ? 1 : 0, pot, field);
   };
   if (field) {
     if (G == 1) p2p(k_p2p<T, true, 1>);

@@ -92,6 +92,7 @@ struct fmm_plan {
   double* radius = nullptr;  // [nbox]
   double* scale = nullptr;   // [nbox] length scale of the box's expansions
   int32_t max_leaf_count = 0;
+  bool has_dup = true;  // some two points coincide (set by the tree build)
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   std::vector<fmm::Step> m2m_steps;  // bottom-up, parents of one level per step
   std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level per step

@@ -47,6 +47,7 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
   U->L = 0;
   U->p2p_inter = 0;
   U->max_leaf_count = 0;
+  U->has_dup = false;
   int64_t n_m2l[2] = {0, 0}, n_p2p[2] = {0, 0}, n_items[2] = {0, 0};
   for (const fmm_plan* p : subs) {
     U->n += p->n;
@@ -55,6 +56,7 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
     U->L = std::max(U->L, p->L);
     U->p2p_inter += p->p2p_inter;
     U->max_leaf_count = std::max(U->max_leaf_count, p->max_leaf_count);
+    U->has_dup = U->has_dup || p->has_dup;
     for (int d = 0; d < 2; ++d) {
       n_m2l[d] += p->lists[d].n_m2l;
       n_p2p[d] += p->lists[d].n_p2p;

@@ -150,6 +150,39 @@ __global__ void k_gather_pos(int n, const int32_t* __restrict__ perm,
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Hash of a position (equal positions give equal hashes; -0 and +0 alike).
+__global__ void k_pos_hash(int n, const double* __restrict__ xs, const double* __restrict__ ys,
+                           const double* __restrict__ zs, uint64_t* __restrict__ h) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto bits = [](double v) { return (uint64_t)__double_as_longlong(v + 0.0); };
+  uint64_t a = bits(xs[i]) * 0x9E3779B97F4A7C15ull;
+  uint64_t b = bits(ys[i]) * 0xC2B2AE3D27D4EB4Full;
+  uint64_t c = bits(zs[i]) * 0x165667B19E3779F9ull;
+  a ^= (b << 21) | (b >> 43);
+  a ^= (c << 42) | (c >> 22);
+  h[i] = a ^ (a >> 29);
+}
+
+// After sorting by hash: flag a pair of coincident points.  Within a run of
+// equal hashes every element is compared with up to kWalk predecessors; a
+// longer run counts as coincident (conservative).
+__global__ void k_dup_check(int n, const uint64_t* __restrict__ h, const int32_t* __restrict__ idx,
+                            const double* __restrict__ xs, const double* __restrict__ ys,
+                            const double* __restrict__ zs, int* __restrict__ flag) {
+  constexpr int kWalk = 32;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 1 || i >= n || h[i] != h[i - 1]) return;
+  const int a = idx[i];
+  for (int j = i - 1, w = 0; j >= 0 && h[j] == h[i]; --j, ++w) {
+    const int b = idx[j];
+    if (w == kWalk || (xs[a] == xs[b] && ys[a] == ys[b] && zs[a] == zs[b])) {
+      *flag = 1;
+      return;
+    }
+  }
+}
+
 // Temporary device memory released when the build ends.
 struct Scratch {
   std::vector<void*> ptrs;
@@ -268,7 +301,16 @@ void build_tree(fmm_plan* pl, const double* pos, hipStream_t st) {
   int mx = 0;
   for (int b = 0; b < nseg; ++b) mx = std::max(mx, seg[b + 1] - seg[b]);
   pl->max_leaf_count = mx;
+  // coincident points anywhere? (P2P then guards every pair, not only the
+  // pairs inside one leaf)
+  k_pos_hash<<<blocks(n, T), T, 0, st>>>(n, pl->xs, pl->ys, pl->zs, keys);
+  sort_pairs_u64_i32(temp, tb, keys, keys_out, iota, lists2[0], n, st);
+  FMM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+  k_dup_check<<<blocks(n, T), T, 0, st>>>(n, keys_out, lists2[0], pl->xs, pl->ys, pl->zs, bad);
+  FMM_HIP(hipGetLastError());
+  FMM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   FMM_HIP(hipStreamSynchronize(st));
+  pl->has_dup = hbad != 0;
 }
 
 }  // namespace fmm

@@ -41,6 +41,14 @@ def _inputs(kind, n, seed):
         return workloads.clustered(n, seed)
     if kind == "plummer":
         return workloads.plummer(n, seed)
+    if kind == "dups":
+        # a uniform cube in which 2% of the points repeat an earlier point
+        pos, q = workloads.uniform_cube(n, seed)
+        rng = np.random.default_rng(seed + 1000)
+        k = max(1, n // 50)
+        dst = rng.choice(np.arange(1, n), k, replace=False)
+        pos[dst] = pos[rng.integers(0, n, k) % np.maximum(dst, 1)]
+        return pos, q
     if kind == "lattice":
         rng = np.random.default_rng(seed)
         return rng.integers(0, 5, (n, 3)).astype(float) * 0.25, rng.uniform(-1, 1, n)
@@ -92,6 +100,7 @@ FMM_CASES = [
     ("cluster", 20000, 8, 64, 2, 0.6),
     ("plummer", 9000, 6, 64, 3, 0.7),
     ("lattice", 2000, 4, 16, 2, 0.6),
+    ("dups", 6000, 6, 32, 3, 0.7),     # coincident points across leaves
     ("cube", 100, 8, 128, 2, 0.6),     # one box: direct sum only
     ("cube", 1, 3, 128, 2, 0.6),       # a single point: zero potential
 ]
@@ -200,6 +209,7 @@ FP32_CASES = [
     ("cluster", 30000, 10, 128, 2, 0.6),   # clustered, sigma = 0.01: scaled expansions
     ("plummer", 20000, 8, 128, 2, 0.6),
     ("lattice", 3000, 6, 16, 2, 0.6),      # coincident points in different leaves
+    ("dups", 8000, 8, 32, 3, 0.7),         # a few coincident pairs among uniform points
     ("cube", 100, 8, 128, 2, 0.6),
 ]
 

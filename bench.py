@@ -41,10 +41,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel_prefix: str):
+def workload_tag(n, p, precision, splits, theta) -> str:
+    """Name of a benchmark configuration in profiles/ file names."""
+    nl = "1m" if n == 1 << 20 else str(n)
+    return f"cube{nl}_p{p}_{precision}_s{splits}_t{int(round(theta * 100))}"
+
+
+def traffic_from_profile(kernel_prefix: str, tag: str):
     """HBM bytes per launch recorded for the dominant kernel under profiles/,
-    if the kernel source has not changed since (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_cube1m_p8_traffic.md")
+    if the kernel sources have not changed since (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_prefix}_{tag}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -52,10 +58,20 @@ def traffic_from_profile(kernel_prefix: str):
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not (m and t):
         return None
-    src = open(os.path.join(ROOT, "paper_2511_15269_amd", "csrc", "eval.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != m.group(1):
+    if kernel_source_hash() != m.group(1):
         return None
     return float(t.group(1))
+
+
+KERNEL_SOURCES = ("eval.hip", "ops.h", "tables.h", "tables.cpp")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources of the single-vector evaluation kernels."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2511_15269_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def cpu_baseline(pos, q, p, leaf, s, theta, n_targets=256):
@@ -89,7 +105,7 @@ def main():
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=128)
     ap.add_argument("--splits", type=int, default=3)
-    ap.add_argument("--theta", type=float, default=0.7)
+    ap.add_argument("--theta", type=float, default=0.8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline (value) pass")
     ap.add_argument("--samples", type=int, default=8192)
@@ -97,6 +113,9 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=2048)
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the FP32 / forward+backward variants")
+    ap.add_argument("--theta-uneven", type=float, default=0.7,
+                    help="separation parameter of the uneven problem set (its small, shallow "
+                         "trees need a smaller theta for 1e-4)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the multi-vector and uneven-problem-set variants")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -240,7 +259,9 @@ def main():
         achieved = flops / (per_stage[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[dtype],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype],
-                "traffic": traffic_from_profile(dom), "kernel": dom,
+                "traffic": traffic_from_profile(
+                    dom, workload_tag(args.n, args.p, head, args.splits, args.theta)),
+                "kernel": dom,
                 "kernel_ms": per_stage[dom], "algorithmic_flops": flops}
 
     cpu = None
@@ -330,7 +351,7 @@ def run_uneven(F, torch, dev, args, timed, rel, k=16):
     N = len(pos)
     pos_d = torch.from_numpy(pos).to(dev)
     qd = torch.from_numpy(q).to(dev).float()
-    kw = dict(p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
+    kw = dict(p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta_uneven,
               precision="fp32")
     plan = F.Plan(pos_d, sizes=sizes, **kw)
     qg = qd.reshape(1, N).clone()
@@ -359,7 +380,8 @@ def run_uneven(F, torch, dev, args, timed, rel, k=16):
     same = bool(torch.equal(g.pot, pot) and torch.equal(g.field, fld))
     out = {
         f"fwd_fp32_uneven{k}_graph": {"ms_per_step": ms_g, "mpoints_s": N / ms_g / 1e3,
-                                      "n_total": N, "sizes": sizes, "rel_l2_pot_max": eu,
+                                      "n_total": N, "sizes": sizes, "theta": args.theta_uneven,
+                                      "rel_l2_pot_max": eu,
                                       "rel_l2_field_max": ef, "graph_equals_eager": same},
         f"fwd_fp32_uneven{k}_eager": {"ms_per_step": ms_e, "mpoints_s": N / ms_e / 1e3},
         f"fwd_fp32_uneven{k}_separate_plans": {"ms_per_step": ms_s, "mpoints_s": N / ms_s / 1e3},

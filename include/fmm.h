@@ -209,11 +209,11 @@ fmm_status fmm_direct(const double* pos, int64_t n, const void* q, int precision
  * (Sec. III.A: sort, mpls, M2M, M2L, L2L, evloc, evdir).  Stage indices:
  *   0 sort (charges to leaf order), 1 P2M, 2 M2M, 3 M2L, 4 L2L,
  *   5 L2P (evloc), 6 P2P (evdir).
- * While enabled, every fmm_evaluate records HIP events on its stream
- * around each stage.  fmm_plan_read_profile waits for those events, writes
- * the summed milliseconds per stage to stage_ms[FMM_NSTAGES] (host) and the
- * number of evaluated passes (charge vectors) to *passes, and clears the
- * record.  Disabling also clears it. */
+ * While enabled, every evaluation records a HIP event before and after each
+ * stage on its stream.  fmm_plan_read_profile waits for those
+ * events, writes the summed milliseconds per stage to
+ * stage_ms[FMM_NSTAGES] (host) and the number of evaluated passes to
+ * *passes, and clears the record.  Disabling also clears it. */
 #define FMM_NSTAGES 7
 fmm_status fmm_plan_set_profiling(fmm_plan* plan, int enable);
 fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,

@@ -504,10 +504,10 @@ fmm_status fmm_plan_read_profile(fmm_plan* pl, double* stage_ms, int64_t* passes
     check_device(pl);
     double acc[FMM_NSTAGES] = {0};
     for (auto& row : pl->ev_rows) {
-      FMM_HIP(hipEventSynchronize(row.back()));
       for (int k = 0; k < FMM_NSTAGES; ++k) {
+        FMM_HIP(hipEventSynchronize(row[2 * k + 1]));
         float ms = 0.f;
-        FMM_HIP(hipEventElapsedTime(&ms, row[k], row[k + 1]));
+        FMM_HIP(hipEventElapsedTime(&ms, row[2 * k], row[2 * k + 1]));
         acc[k] += ms;
       }
     }

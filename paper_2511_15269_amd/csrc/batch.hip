@@ -348,43 +348,41 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   float* potL = (float*)pl->bpot;
   float* fldL = (float*)pl->bfld;
   const int64_t n = pl->n;
-  std::vector<hipEvent_t>* row = nullptr;
-  if (pl->profiling) {
-    pl->ev_rows.emplace_back();
-    row = &pl->ev_rows.back();
-    for (int k = 0; k <= FMM_NSTAGES; ++k) row->push_back(take_event(pl));
-  }
-  auto mark = [&](int k) {
-    if (row) FMM_HIP(hipEventRecord((*row)[k], st));
-  };
-  mark(0);
+  StageMarks mk(pl);
+  mk.begin(kStSort, st);
   k_bgather<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, q, qL);
-  mark(1);
+  mk.end(kStSort, st);
+  mk.begin(kStP2M, st);
   k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
                                                 pl->zs, qL, pl->cx, pl->cy, pl->cz, pl->scale,
                                                 tab, C);
-  mark(2);
+  mk.end(kStP2M, st);
+  mk.begin(kStM2M, st);
   for (const Step& S : pl->m2m_steps)
     k_bm2m<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
                                              pl->scale, tab, C);
-  mark(3);
+  mk.end(kStM2M, st);
+  mk.begin(kStM2L, st);
   if (Ls.n_items > 0)
     k_bm2l<P><<<blocks(Ls.n_items, 2), 64, 0, st>>>(Ls.n_items, Ls.item_tgt, Ls.item_begin,
                                                     Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
                                                     pl->cz, pl->scale, C, tab, part);
-  mark(4);
+  mk.end(kStM2L, st);
+  mk.begin(kStL2L, st);
   for (const Step& S : pl->l2l_steps)
     k_bl2l<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
                                              pl->cz, pl->scale, tab, D);
-  mark(5);
+  mk.end(kStL2L, st);
+  mk.begin(kStL2P, st);
   k_bl2p<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
                                                 pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D,
                                                 tab, potL, fldL);
-  mark(6);
+  mk.end(kStL2P, st);
+  mk.begin(kStP2P, st);
   k_bp2p<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->xs, pl->ys, pl->zs, qL,
                                               Ls.p2p_ptr, Ls.p2p_src, potL, fldL);
   k_bscatter<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, potL, fldL, pot, field);
-  mark(7);
+  mk.end(kStP2P, st);
   FMM_HIP(hipGetLastError());
 }
 

@@ -200,8 +200,8 @@ __global__ __launch_bounds__(64) void k_l2l(
 // ---------------------------------------------------------------- L2P
 // L2P: u = -1/(4 pi) (1/rho) sum w_m D R-hat(y), y = (x - c)/rho, and
 // field = -grad u (an extra 1/rho from the chain rule), at every point of the
-// target leaf; writes (not adds) the outputs in input order.  G leaves per
-// wave, LW = 64/G lanes each, lane = point.
+// target leaf, added to the near-field values P2P has written (input order).
+// G leaves per wave, LW = 64/G lanes each, lane = point.
 template <int P, typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_l2p(
     int64_t nleaf, const int32_t* __restrict__ leaf_box,
@@ -233,11 +233,11 @@ __global__ __launch_bounds__(64) void k_l2p(
     local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w[h],
                      fp, fx, fy, fz);
     const int o = perm[i];
-    pot[o] = fu * fp;
+    pot[o] += fu * fp;
     if (FIELD) {
-      field[3 * (int64_t)o + 0] = ff * fx;
-      field[3 * (int64_t)o + 1] = ff * fy;
-      field[3 * (int64_t)o + 2] = ff * fz;
+      field[3 * (int64_t)o + 0] += ff * fx;
+      field[3 * (int64_t)o + 1] += ff * fy;
+      field[3 * (int64_t)o + 2] += ff * fz;
     }
   }
 }
@@ -265,7 +265,8 @@ __device__ __forceinline__ void p2p_pair(const Src<T>& s, double xi, double yi, 
 
 constexpr int kChunk = 8;
 
-// P2P: adds -1/(4 pi) sum q/r and the matching field over the direct list.
+// P2P: writes -1/(4 pi) sum q/r and the matching field over the direct list
+// (the first writer of the outputs; L2P adds the far field).
 // Block = target leaf, lane = target point.  G source groups: lanes
 // [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
 // G-th source point starting at point g.  G = 1 keeps all source reads
@@ -366,12 +367,12 @@ __global__ __launch_bounds__(64) void k_p2p(
     }
     if (live && g == 0) {
       const int o = perm[i];
-      pot[o] += -T(kInv4Pi) * u;
+      pot[o] = -T(kInv4Pi) * u;
       if (FIELD) {
         // field = -grad u;  grad of the near part is +(1/4pi) sum q d/r^3
-        field[3 * (int64_t)o + 0] -= T(kInv4Pi) * gx;
-        field[3 * (int64_t)o + 1] -= T(kInv4Pi) * gy;
-        field[3 * (int64_t)o + 2] -= T(kInv4Pi) * gz;
+        field[3 * (int64_t)o + 0] = -T(kInv4Pi) * gx;
+        field[3 * (int64_t)o + 1] = -T(kInv4Pi) * gy;
+        field[3 * (int64_t)o + 2] = -T(kInv4Pi) * gz;
       }
     }
   }
@@ -402,6 +403,10 @@ __global__ void k_adjoint_combine(int64_t n, const T* __restrict__ q, const T* _
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// One evaluation, every stage on the caller's stream: P2P writes the near
+// field, L2P adds the far field.  (Running P2P concurrently on a second
+// stream does not pay: it fills the GPU and delays the small level-by-level
+// launches of the far field by as much as it hides.)
 template <int P, typename T>
 void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStream_t st) {
   const int s = pl->s;
@@ -411,23 +416,17 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   T* D = (T*)pl->D;
   T* part = (T*)pl->partial;
   const int64_t n = pl->n;
-  std::vector<hipEvent_t>* row = nullptr;
-  if (pl->profiling) {
-    pl->ev_rows.emplace_back();
-    row = &pl->ev_rows.back();
-    for (int k = 0; k <= FMM_NSTAGES; ++k) row->push_back(take_event(pl));
-  }
-  auto mark = [&](int k) {
-    if (row) FMM_HIP(hipEventRecord((*row)[k], st));
-  };
-  mark(0);
+  StageMarks mk(pl);
+  mk.begin(kStSort, st);
   k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
-  mark(1);
+  mk.end(kStSort, st);
+  // far field
   // leaves per wave for P2M and L2P: every lane holds at most one point
   const int mlc = pl->max_leaf_count;
   const int GL = mlc > 32 ? 1 : (mlc > 16 ? 2 : (mlc > 8 ? 4 : 8));
   const int64_t nl = pl->nleaf;
   const unsigned nb_l = (unsigned)((nl + GL - 1) / GL);
+  mk.begin(kStP2M, st);
   auto p2m = [&](auto kern) {
     kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs, src,
                               pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
@@ -436,22 +435,43 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   else if (GL == 2) p2m(k_p2m<P, T, 2>);
   else if (GL == 4) p2m(k_p2m<P, T, 4>);
   else p2m(k_p2m<P, T, 8>);
-  mark(2);
+  mk.end(kStP2M, st);
+  mk.begin(kStM2M, st);
   for (const Step& S : pl->m2m_steps) {
     const int64_t nchild = S.n << s;
     k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
                                                    pl->scale, tab, C);
   }
-  mark(3);
+  mk.end(kStM2M, st);
+  mk.begin(kStM2L, st);
   if (Ls.n_items > 0)
     k_m2l<P, T><<<blocks(Ls.n_items, kM2LThreads), kM2LThreads, 0, st>>>(
         Ls.n_items, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
         pl->cz, pl->scale, C, tab, part);
-  mark(4);
+  mk.end(kStM2L, st);
+  mk.begin(kStL2L, st);
   for (const Step& S : pl->l2l_steps)
     k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
                                                 pl->cz, pl->scale, tab, D);
-  mark(5);
+  mk.end(kStL2L, st);
+  // near field
+  mk.begin(kStP2P, st);
+  const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
+  auto p2p = [&](auto kern) {
+    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, Ls.p2p_ptr,
+                                                Ls.p2p_src, pl->has_dup ? 1 : 0, pot, field);
+  };
+  if (field) {
+    if (G == 1) p2p(k_p2p<T, true, 1>);
+    else if (G == 2) p2p(k_p2p<T, true, 2>);
+    else p2p(k_p2p<T, true, 4>);
+  } else {
+    if (G == 1) p2p(k_p2p<T, false, 1>);
+    else if (G == 2) p2p(k_p2p<T, false, 2>);
+    else p2p(k_p2p<T, false, 4>);
+  }
+  mk.end(kStP2P, st);
+  mk.begin(kStL2P, st);
   auto l2p = [&](auto kern) {
     kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys,
                               pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, pot, field);
@@ -467,22 +487,7 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
     else if (GL == 4) l2p(k_l2p<P, T, false, 4>);
     else l2p(k_l2p<P, T, false, 8>);
   }
-  mark(6);
-  const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
-  auto p2p = [&](auto kern) {
-    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, Ls.p2p_ptr,
-                                              Ls.p2p_src, pl->has_dup ? 1 : 0, pot, field);
-  };
-  if (field) {
-    if (G == 1) p2p(k_p2p<T, true, 1>);
-    else if (G == 2) p2p(k_p2p<T, true, 2>);
-    else p2p(k_p2p<T, true, 4>);
-  } else {
-    if (G == 1) p2p(k_p2p<T, false, 1>);
-    else if (G == 2) p2p(k_p2p<T, false, 2>);
-    else p2p(k_p2p<T, false, 4>);
-  }
-  mark(7);
+  mk.end(kStL2P, st);
   FMM_HIP(hipGetLastError());
 }
 

@@ -124,7 +124,7 @@ struct fmm_plan {
   // stage timing (fmm_plan_set_profiling)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;               // free events
-  std::vector<std::vector<hipEvent_t>> ev_rows;  // FMM_NSTAGES+1 per pass
+  std::vector<std::vector<hipEvent_t>> ev_rows;  // 2 FMM_NSTAGES per pass
 };
 
 // Captured evaluation (fmm_graph_create).
@@ -179,6 +179,24 @@ void direct_sum(int64_t n, const double* pos, const void* q, int precision,
 // Stage-timing helpers (api.cpp).
 hipEvent_t take_event(fmm_plan* pl);
 void release_profile(fmm_plan* pl);
+enum { kStSort = 0, kStP2M, kStM2M, kStM2L, kStL2L, kStL2P, kStP2P };
+// Begin/end events of every stage of one pass (when profiling is on), each
+// pair recorded on the stream the stage runs on.
+struct StageMarks {
+  std::vector<hipEvent_t>* row = nullptr;
+  explicit StageMarks(fmm_plan* pl) {
+    if (!pl->profiling) return;
+    pl->ev_rows.emplace_back();
+    row = &pl->ev_rows.back();
+    for (int k = 0; k < 2 * FMM_NSTAGES; ++k) row->push_back(take_event(pl));
+  }
+  void begin(int k, hipStream_t s) const {
+    if (row) FMM_HIP(hipEventRecord((*row)[2 * k], s));
+  }
+  void end(int k, hipStream_t s) const {
+    if (row) FMM_HIP(hipEventRecord((*row)[2 * k + 1], s));
+  }
+};
 
 // Sorting primitives (sort.hip).
 size_t sort_pairs_u64_i32_temp(int n);

@@ -260,6 +260,7 @@ void alloc_workspace(fmm_plan* pl, hipStream_t st) {
   pl->D = plan_alloc(pl, es * K * (size_t)pl->nbox);
   pl->partial = plan_alloc(pl, es * K * ni);
   pl->field_t = plan_alloc(pl, es * 3 * (size_t)n);
+  pl->near = plan_alloc(pl, es * 4 * (size_t)n);
   if (prm->precision == FMM_FP32 && prm->max_rhs > 1) {
     const size_t W = (size_t)batch_width() * sizeof(float);
     pl->bq = plan_alloc(pl, W * n);

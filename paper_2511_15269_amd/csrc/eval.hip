@@ -141,7 +141,8 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
     const double* __restrict__ scale, const T* __restrict__ C,
     const T* __restrict__ tab, T* __restrict__ partial) {
   constexpr int K = K_<P>::value;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i =
+      (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const int t = item_tgt[i];
   const int jb = item_begin[i], je = item_end[i];
@@ -200,8 +201,9 @@ __global__ __launch_bounds__(64) void k_l2l(
 // ---------------------------------------------------------------- L2P
 // L2P: u = -1/(4 pi) (1/rho) sum w_m D R-hat(y), y = (x - c)/rho, and
 // field = -grad u (an extra 1/rho from the chain rule), at every point of the
-// target leaf, added to the near-field values P2P has written (input order).
-// G leaves per wave, LW = 64/G lanes each, lane = point.
+// target leaf, added to the near field P2P left in leaf order; writes the
+// outputs in input order.  G leaves per wave, LW = 64/G lanes each, lane =
+// point.
 template <int P, typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_l2p(
     int64_t nleaf, const int32_t* __restrict__ leaf_box,
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(64) void k_l2p(
     const double* __restrict__ zs, const double* __restrict__ cx,
     const double* __restrict__ cy, const double* __restrict__ cz,
     const double* __restrict__ scale, const T* __restrict__ D, const T* __restrict__ tab,
-    T* __restrict__ pot, T* __restrict__ field) {
+    int64_t n, const T* __restrict__ near, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int K = K_<P>::value;
   constexpr int LW = 64 / G;
   __shared__ T w[G][K];
@@ -233,11 +235,12 @@ __global__ __launch_bounds__(64) void k_l2p(
     local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w[h],
                      fp, fx, fy, fz);
     const int o = perm[i];
-    pot[o] += fu * fp;
+    pot[o] = near[i] + fu * fp;
     if (FIELD) {
-      field[3 * (int64_t)o + 0] += ff * fx;
-      field[3 * (int64_t)o + 1] += ff * fy;
-      field[3 * (int64_t)o + 2] += ff * fz;
+      const T* f = near + n + 3 * (int64_t)i;
+      field[3 * (int64_t)o + 0] = f[0] + ff * fx;
+      field[3 * (int64_t)o + 1] = f[1] + ff * fy;
+      field[3 * (int64_t)o + 2] = f[2] + ff * fz;
     }
   }
 }
@@ -265,8 +268,9 @@ __device__ __forceinline__ void p2p_pair(const Src<T>& s, double xi, double yi, 
 
 constexpr int kChunk = 8;
 
-// P2P: writes -1/(4 pi) sum q/r and the matching field over the direct list
-// (the first writer of the outputs; L2P adds the far field).
+// P2P: writes -1/(4 pi) sum q/r and the matching field over the direct list,
+// in leaf order (near[i] and near[n + 3 i + c]); L2P adds the far field and
+// writes the outputs in input order.
 // Block = target leaf, lane = target point.  G source groups: lanes
 // [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
 // G-th source point starting at point g.  G = 1 keeps all source reads
@@ -279,9 +283,9 @@ constexpr int kChunk = 8;
 // combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
-    const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ perm,
-    const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
-    const int32_t* __restrict__ p2p_src, int dup, T* __restrict__ pot, T* __restrict__ field) {
+    int64_t n, const int32_t* __restrict__ leaf_start, const Src<T>* __restrict__ src,
+    const int32_t* __restrict__ p2p_ptr, const int32_t* __restrict__ p2p_src, int dup,
+    T* __restrict__ near) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   // G > 1: one source leaf (at most TL points) staged as 16-byte words
@@ -366,13 +370,13 @@ __global__ __launch_bounds__(64) void k_p2p(
       }
     }
     if (live && g == 0) {
-      const int o = perm[i];
-      pot[o] = -T(kInv4Pi) * u;
+      near[i] = -T(kInv4Pi) * u;
       if (FIELD) {
         // field = -grad u;  grad of the near part is +(1/4pi) sum q d/r^3
-        field[3 * (int64_t)o + 0] = -T(kInv4Pi) * gx;
-        field[3 * (int64_t)o + 1] = -T(kInv4Pi) * gy;
-        field[3 * (int64_t)o + 2] = -T(kInv4Pi) * gz;
+        T* f = near + n + 3 * (int64_t)i;
+        f[0] = -T(kInv4Pi) * gx;
+        f[1] = -T(kInv4Pi) * gy;
+        f[2] = -T(kInv4Pi) * gz;
       }
     }
   }
@@ -404,7 +408,7 @@ __global__ void k_adjoint_combine(int64_t n, const T* __restrict__ q, const T* _
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // One evaluation, every stage on the caller's stream: P2P writes the near
-// field, L2P adds the far field.  (Running P2P concurrently on a second
+// field in leaf order, L2P adds the far field and writes the outputs.  (Running P2P concurrently on a second
 // stream does not pay: it fills the GPU and delays the small level-by-level
 // launches of the far field by as much as it hides.)
 template <int P, typename T>
@@ -415,6 +419,7 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   T* C = (T*)pl->C;
   T* D = (T*)pl->D;
   T* part = (T*)pl->partial;
+  T* near = (T*)pl->near;
   const int64_t n = pl->n;
   StageMarks mk(pl);
   mk.begin(kStSort, st);
@@ -458,8 +463,8 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.begin(kStP2P, st);
   const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
   auto p2p = [&](auto kern) {
-    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->perm, src, Ls.p2p_ptr,
-                                                Ls.p2p_src, pl->has_dup ? 1 : 0, pot, field);
+    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(n, pl->leaf_start, src, Ls.p2p_ptr, Ls.p2p_src,
+                                              pl->has_dup ? 1 : 0, near);
   };
   if (field) {
     if (G == 1) p2p(k_p2p<T, true, 1>);
@@ -474,7 +479,8 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.begin(kStL2P, st);
   auto l2p = [&](auto kern) {
     kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys,
-                              pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, pot, field);
+                              pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, n, near, pot,
+                              field);
   };
   if (field) {
     if (GL == 1) l2p(k_l2p<P, T, true, 1>);

@@ -109,6 +109,7 @@ struct fmm_plan {
   void* D = nullptr;         // [nbox][K]   locals (normalised)
   void* partial = nullptr;   // [max n_items][K] M2L partial sums
   void* field_t = nullptr;   // [n][3] field of the transposed pass (adjoint)
+  void* near = nullptr;      // [4n] near field in leaf order: pot [n], field [n][3]
   // multi-vector workspace (FP32 plans with max_rhs > 1), vectors innermost
   void* bq = nullptr;     // [n][32]
   void* bC = nullptr;     // [nbox][K][32]

@@ -416,6 +416,19 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
 }
 __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+// ------------------------------------------------------ block placement
+// Workgroups are handed to the 8 XCDs round robin (block b to XCD b % 8),
+// each XCD with its own L2.  This maps block b to a logical index so that
+// every XCD works through one contiguous range of the logical blocks, and
+// neighbouring work (which shares expansions and source points) shares an
+// L2.  A bijection on [0, nb) for any nb.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  constexpr unsigned kXcd = 8;
+  const unsigned q = nb / kXcd, r = nb % kXcd;
+  const unsigned x = b % kXcd, j = b / kXcd;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // ------------------------------------------------------ lane reductions
 // Cross-lane moves through the VALU's data-parallel primitives (no LDS).
 // CTRL: quad_perm / row_mirror / row_bcast selector; RM: rows written (the

@@ -119,7 +119,11 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
     S.b = upload(b);
     pl->m2m_steps.push_back(S);
   }
-  // Downward: step l takes level l of every tree that deep.
+  // Downward: every box whose local is formed starts from the sum of its
+  // M2L partials (one launch over all of them); step l then adds the
+  // translated parent local to the boxes of level l of every tree that deep
+  // whose parent has one.
+  std::vector<int32_t> all;
   for (int l = 0; l <= Lmax; ++l) {
     std::vector<int32_t> a, b;
     for (const TreeDesc& t : trees) {
@@ -128,9 +132,11 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
       for (int64_t i = 0; i < nb; ++i) {
         const int64_t bx = t.box_base + t.level_off[l] + i;
         if (!active[bx] && l < t.L) continue;  // leaves are always written
+        all.push_back((int32_t)bx);
         const int64_t pa = l > 0 ? t.box_base + t.level_off[l - 1] + (i >> s) : -1;
+        if (pa < 0 || !active[pa]) continue;
         a.push_back((int32_t)bx);
-        b.push_back(pa >= 0 && active[pa] ? (int32_t)pa : -1);
+        b.push_back((int32_t)pa);
       }
     }
     if (a.empty()) continue;
@@ -140,6 +146,9 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
     S.b = upload(b);
     pl->l2l_steps.push_back(S);
   }
+  pl->l2l_sum.n = (int64_t)all.size();
+  pl->l2l_sum.a = upload(all);
+  pl->l2l_sum.b = nullptr;
 }
 
 namespace {

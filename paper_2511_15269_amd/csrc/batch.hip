@@ -170,34 +170,22 @@ __global__ __launch_bounds__(64) void k_bm2l(
 template <int P>
 __global__ __launch_bounds__(64) void k_bl2l(
     int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
-    const int32_t* __restrict__ item_ptr,
-    const float* __restrict__ partial, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
-    const double* __restrict__ scale, const float* __restrict__ tab, float* D) {
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const float* __restrict__ tab, float* D) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * 2 + threadIdx.x / kRB;
   const int r = threadIdx.x % kRB;
   if (i >= nb) return;
   const int64_t t = boxes[i];
-  float acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.f;
-  for (int it = item_ptr[t]; it < item_ptr[t + 1]; ++it) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += partial[((int64_t)it * K + k) * kRB + r];
-  }
   const int64_t pa = parents[i];
-  if (pa >= 0) {
-    float v[K];
+  float v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = D[(pa * K + k) * kRB + r];
-    rotate_shift<P, kL2L, float>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
-                                 scale[t], tab);
+  for (int k = 0; k < K; ++k) v[k] = D[(pa * K + k) * kRB + r];
+  rotate_shift<P, kL2L, float>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
+                               scale[t], tab);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v[k];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) D[(t * K + k) * kRB + r] = acc[k];
+  for (int k = 0; k < K; ++k) D[(t * K + k) * kRB + r] = D[(t * K + k) * kRB + r] + v[k];
 }
 
 // L2P for 32 points at a time: basis and gradient in LDS, lane r sums.
@@ -369,9 +357,12 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                                                     pl->cz, pl->scale, C, tab, part);
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
+  if (pl->l2l_sum.n > 0)
+    k_psum<float><<<(unsigned)pl->l2l_sum.n, 256, 0, st>>>(
+        pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr, part, K_<P>::value * kRB, D);
   for (const Step& S : pl->l2l_steps)
-    k_bl2l<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
-                                             pl->cz, pl->scale, tab, D);
+    k_bl2l<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz, pl->scale,
+                                             tab, D);
   mk.end(kStL2L, st);
   mk.begin(kStL2P, st);
   k_bl2p<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,

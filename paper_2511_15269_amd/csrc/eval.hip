@@ -165,11 +165,11 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
 }
 
 // ---------------------------------------------------------------- L2L
-// D_t = (M2L partials of t, in item order) + L2L(D_parent)
+// D_t += L2L(D_parent) for the boxes of one level (D_t holds the sum of
+// t's M2L partials, k_psum).
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_l2l(
     int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
-    const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
     const double* __restrict__ cx, const double* __restrict__ cy,
     const double* __restrict__ cz, const double* __restrict__ scale,
     const T* __restrict__ tab, T* D) {
@@ -177,25 +177,14 @@ __global__ __launch_bounds__(64) void k_l2l(
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const int64_t t = boxes[i];
-  T acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = T(0);
-  for (int it = item_ptr[t]; it < item_ptr[t + 1]; ++it) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += partial[(int64_t)it * K + k];
-  }
   const int64_t pa = parents[i];
-  if (pa >= 0) {
-    T v[K];
+  T v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
-    rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
-                             scale[t], tab);
+  for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
+  rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
+                           scale[t], tab);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v[k];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) D[t * K + k] = acc[k];
+  for (int k = 0; k < K; ++k) D[t * K + k] = D[t * K + k] + v[k];
 }
 
 // ---------------------------------------------------------------- L2P
@@ -455,9 +444,12 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
         pl->cz, pl->scale, C, tab, part);
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
+  if (pl->l2l_sum.n > 0)
+    k_psum<T><<<(unsigned)pl->l2l_sum.n, 64, 0, st>>>(pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr,
+                                                      part, K_<P>::value, D);
   for (const Step& S : pl->l2l_steps)
-    k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, Ls.item_ptr, part, pl->cx, pl->cy,
-                                                pl->cz, pl->scale, tab, D);
+    k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz,
+                                                pl->scale, tab, D);
   mk.end(kStL2L, st);
   // near field
   mk.begin(kStP2P, st);

@@ -95,7 +95,8 @@ struct fmm_plan {
   bool has_dup = true;  // some two points coincide (set by the tree build)
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   std::vector<fmm::Step> m2m_steps;  // bottom-up, parents of one level per step
-  std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level per step
+  std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level with a parent local
+  fmm::Step l2l_sum;                 // every box whose local is formed (b unused)
   int n_problems = 1;                // > 1: union of independent trees
 
   // lists (device): [0] forward, [1] transposed (every pair reversed; the

@@ -416,6 +416,24 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
 }
 __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
+// ------------------------------------------------------ M2L partial sums
+// D[t][0..W) = sum over the M2L work items of box t (in item order) of
+// their partial rows, for every box t in boxes[0..nb): one block per box,
+// threads over the row.  The far-field local of every box starts here; the
+// level-by-level L2L kernels then add the translated parent local.
+template <typename T>
+__global__ void k_psum(int64_t nb, const int32_t* __restrict__ boxes,
+                       const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
+                       int W, T* __restrict__ D) {
+  const int64_t t = boxes[blockIdx.x];
+  const int b = item_ptr[t], e = item_ptr[t + 1];
+  for (int k = threadIdx.x; k < W; k += blockDim.x) {
+    T acc = T(0);
+    for (int it = b; it < e; ++it) acc += partial[(int64_t)it * W + k];
+    D[t * W + k] = acc;
+  }
+}
+
 // ------------------------------------------------------ block placement
 // Workgroups are handed to the 8 XCDs round robin (block b to XCD b % 8),
 // each XCD with its own L2.  This maps block b to a logical index so that

@@ -147,9 +147,19 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
   const int t = item_tgt[i];
   const int jb = item_begin[i], je = item_end[i];
   const double tx = cx[t], ty = cy[t], tz = cz[t], rt = scale[t];
-  T acc[K];
+  // Accumulators: in FP64 with (p+1)^2 > 80 the first 80 coefficients live
+  // in LDS (lane-private slots, coefficient-major so that a wave's 64 slots
+  // are consecutive; 40 KiB per 64-lane block, four blocks fill a CU's
+  // 160 KiB, the occupancy the registers allow anyway) and are updated with
+  // LDS atomic adds that need no registers; the rest stay in registers.
+  constexpr int KL = (sizeof(T) == 8 && K > 80) ? 80 : 0;
+  __shared__ T accl[KL > 0 ? KL : 1][64];
+  const int lane = threadIdx.x;
+  T acc[K - KL];
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  for (int k = 0; k < KL; ++k) accl[k][lane] = T(0);
+#pragma unroll
+  for (int k = 0; k < K - KL; ++k) acc[k] = T(0);
   for (int j = jb; j < je; ++j) {
     const int sidx = src[j];
     T v[K];
@@ -158,10 +168,15 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
     rotate_shift<P, kM2L, T>(v, cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, scale[sidx], rt,
                              tab);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v[k];
+    for (int k = 0; k < KL; ++k)
+      __hip_atomic_fetch_add(&accl[k][lane], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int k = KL; k < K; ++k) acc[k - KL] += v[k];
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) partial[i * K + k] = acc[k];
+  for (int k = 0; k < KL; ++k) partial[i * K + k] = accl[k][lane];
+#pragma unroll
+  for (int k = KL; k < K; ++k) partial[i * K + k] = acc[k - KL];
 }
 
 // ---------------------------------------------------------------- L2L

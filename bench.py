@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=2048)
     ap.add_argument("--only-headline", action="store_true",
                     help="skip the FP32 / forward+backward variants")
-    ap.add_argument("--theta-uneven", type=float, default=0.7,
+    ap.add_argument("--theta-uneven", type=float, default=0.6,
                     help="separation parameter of the uneven problem set (its small, shallow "
                          "trees need a smaller theta for 1e-4)")
     ap.add_argument("--no-batched", action="store_true",

@@ -108,7 +108,9 @@ def main():
     ap.add_argument("--theta", type=float, default=0.8)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline (value) pass")
-    ap.add_argument("--samples", type=int, default=8192)
+    ap.add_argument("--samples", type=int, default=0,
+                    help="targets of the accuracy check against the FP64 direct sum "
+                         "(0: every point)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=2048)
     ap.add_argument("--only-headline", action="store_true",
@@ -139,7 +141,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     # FP64 direct sum at sampled targets: the accuracy reference of every variant
-    tg = workloads.sample_targets(args.n, args.samples, seed=1)
+    tg = (np.arange(args.n) if args.samples <= 0
+          else workloads.sample_targets(args.n, args.samples, seed=1))
     tg_d = torch.from_numpy(tg).to(dev)
     ud, fd = F.direct(pos_d, q64, tg_d)
     torch.cuda.synchronize()
@@ -288,7 +291,7 @@ def main():
                                f"potential+field, {head} forward pass on a cached plan",
                    "n": args.n, "p": args.p, "leaf_max": args.leaf, "splits": args.splits,
                    "theta": args.theta, "precision": head},
-        "accuracy": {**acc, "samples": args.samples, "reference": "direct sum (FP64)"},
+        "accuracy": {**acc, "targets": len(tg), "reference": "direct sum (FP64), library kernel"},
         "variants": res_variants,
         "stage_ms": per_stage,
         "plan_build_ms": plan_ms,
@@ -320,7 +323,7 @@ def run_batched(F, torch, dev, args, timed, rel, n=1 << 18, R=32):
         for r in range(R):
             single.evaluate(Qd[r:r + 1], out=(p1, f1))
     ms_s = timed(singles, max(1, args.steps // 4), 1)
-    tg = workloads.sample_targets(n, 2048, seed=1)
+    tg = np.arange(n)
     tg_d = torch.from_numpy(tg).to(dev)
     acc = {}
     for r in (0, R - 1):
@@ -371,8 +374,8 @@ def run_uneven(F, torch, dev, args, timed, rel, k=16):
     ms_s = timed(separate, args.steps, args.warmup)
     torch.cuda.synchronize()
     eu = ef = 0.0
-    for j in (int(np.argmin(sizes)), int(np.argmax(sizes))):
-        tg = workloads.sample_targets(sizes[j], 1024, seed=1)
+    for j in range(k):
+        tg = np.arange(sizes[j])
         ud, fd = F.direct(pos_d[off[j]:off[j + 1]],
                           torch.from_numpy(parts[j][1]).to(dev), torch.from_numpy(tg).to(dev))
         eu = max(eu, rel(g.pot[0, off[j] + tg].double().cpu().numpy(), ud.cpu().numpy()))

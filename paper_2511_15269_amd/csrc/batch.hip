@@ -25,6 +25,8 @@
 //         zero and added to the running sums with Neumaier compensation.
 #include <cmath>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "ops.h"
 #include "tables.h"
@@ -36,10 +38,21 @@ using namespace ops;
 constexpr int kRB = 32;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Neumaier's compensated addition, elementwise: s + c carries the sum.
+__device__ __forceinline__ void neumaier4(floatx4& s, floatx4& c, floatx4 x) {
+  const floatx4 t = s + x;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float sv = s[v], xv = x[v], tv = t[v];
+    c[v] += fabsf(sv) >= fabsf(xv) ? (sv - tv) + xv : (xv - tv) + sv;
+  }
+  s = t;
+}
+
 __device__ __forceinline__ void neumaier16(floatx16& s, floatx16& c, floatx16 x) {
   const floatx16 t = s + x;
 #pragma unroll
@@ -243,66 +256,124 @@ __global__ __launch_bounds__(64) void k_bl2p(
   }
 }
 
-// P2P on the matrix cores.  For a tile of 32 targets (rows) and 32 vectors
-// (columns), every step takes two source points: lane l computes the kernel
-// entries of target (l % 32) and source (l / 32) -- the A operand -- and
-// supplies the charge of source (l / 32) for vector (l % 32) -- the B
-// operand.  Accumulator register v of lane l holds row
-// 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
-__global__ __launch_bounds__(64) void k_bp2p(
+// P2P on the matrix cores (v_mfma_f32_16x16x4f32).  A tile is 16 targets
+// (rows) x 32 vectors (columns, two 16-column halves); every step takes four
+// source points: lane l computes the kernel entries of target (l % 16) and
+// source (l / 16) -- the A operand -- and supplies the charges of source
+// (l / 16) for vectors (l % 16) and 16 + (l % 16) -- the B operands of the
+// two halves.  Accumulator register v of lane l holds row 4 (l / 16) + v,
+// column l % 16 (+16 in the second half).  Source points (positions and the
+// 32 charges) are staged in LDS, up to kStage points at a time, with
+// coalesced loads.  A block holds TW waves, one 16-target tile each, that
+// share every staged chunk.  Small tiles keep the accumulators to 32
+// registers per lane, so two waves share a SIMD.
+constexpr int kStage = 64;
+
+template <int TW>
+__global__ __launch_bounds__(64 * TW) void k_bp2p(
     const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs,
     const float* __restrict__ qL, const int32_t* __restrict__ p2p_ptr,
     const int32_t* __restrict__ p2p_src, float* __restrict__ potL, float* __restrict__ fldL) {
+  __shared__ double px[kStage], py[kStage], pz[kStage];
+  // charge rows padded to 48 floats: the four source rows a step reads sit
+  // 16 banks apart, so a half-wave's 32 lanes hit 32 distinct banks
+  constexpr int kQS = kRB + 16;
+  __shared__ __align__(16) float qs[kStage][kQS];
   const int leaf = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int row = lane % 32, kk = lane / 32;
+  const int tid = threadIdx.x;
+  const int lane = tid % 64, wv = tid / 64;
+  const int row = lane % 16, kk = lane / 16;
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
-  for (int i0 = st; i0 < en; i0 += 32) {
+  // every wave runs the same number of tiles (barriers inside)
+  const int ntile = (en - st + 16 * TW - 1) / (16 * TW);
+  for (int tl = 0; tl < ntile; ++tl) {
+    const int i0 = st + 16 * (tl * TW + wv);
     const int i = i0 + row;
     const bool live_i = i < en;
     const int ii = live_i ? i : st;
     const double xi = xs[ii], yi = ys[ii], zi = zs[ii];
-    // running sums (s*) with Neumaier compensation (c*); each source leaf is
-    // accumulated on the matrix cores from zero and then added
-    floatx16 su = {}, sx = {}, sy = {}, sz = {}, cu = {}, cx_ = {}, cy_ = {}, cz_ = {};
+    // running sums (s*) with Neumaier compensation (c*) for the two column
+    // halves (0, 1); each source leaf is accumulated on the matrix cores
+    // from zero and then added
+    floatx4 su0 = {}, sx0 = {}, sy0 = {}, sz0 = {}, su1 = {}, sx1 = {}, sy1 = {}, sz1 = {};
+    floatx4 cu0 = {}, cx0 = {}, cy0 = {}, cz0 = {}, cu1 = {}, cx1 = {}, cy1 = {}, cz1 = {};
     for (int k = pb; k < pe; ++k) {
       const int sl = p2p_src[k];
       const int js = leaf_start[sl], je = leaf_start[sl + 1];
-      floatx16 au = {}, ax = {}, ay = {}, az = {};
-      for (int j0 = js; j0 < je; j0 += 2) {
-        const int j = j0 + kk;
-        const bool live_j = j < je;
-        const int jj = live_j ? j : js;
-        const float dx = float(xi - xs[jj]), dy = float(yi - ys[jj]), dz = float(zi - zs[jj]);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float inv0 = __builtin_amdgcn_rsqf(r2);
-        const float inv = (r2 > 0.f && live_i && live_j) ? inv0 : 0.f;
-        const float inv3 = inv * inv * inv;
-        const float b = live_j ? qL[(int64_t)jj * kRB + row] : 0.f;
-        au = __builtin_amdgcn_mfma_f32_32x32x2f32(inv, b, au, 0, 0, 0);
-        ax = __builtin_amdgcn_mfma_f32_32x32x2f32(dx * inv3, b, ax, 0, 0, 0);
-        ay = __builtin_amdgcn_mfma_f32_32x32x2f32(dy * inv3, b, ay, 0, 0, 0);
-        az = __builtin_amdgcn_mfma_f32_32x32x2f32(dz * inv3, b, az, 0, 0, 0);
+      floatx4 au0 = {}, ax0 = {}, ay0 = {}, az0 = {}, au1 = {}, ax1 = {}, ay1 = {}, az1 = {};
+      for (int c0 = js; c0 < je; c0 += kStage) {
+        const int cnt = min(kStage, je - c0);
+        __syncthreads();  // the previous chunk's reads are done
+        if (tid < cnt) {
+          px[tid] = xs[c0 + tid];
+          py[tid] = ys[c0 + tid];
+          pz[tid] = zs[c0 + tid];
+        }
+        {
+          const float4* from = reinterpret_cast<const float4*>(qL + (int64_t)c0 * kRB);
+          for (int e = tid; e < cnt * (kRB / 4); e += 64 * TW)
+            *reinterpret_cast<float4*>(&qs[e / (kRB / 4)][4 * (e % (kRB / 4))]) = from[e];
+        }
+        __syncthreads();
+        // one step: four source points j0 .. j0+3 (lane group kk takes j0+kk)
+        auto step = [&](int j0, auto check_tag) {
+          constexpr bool CHECK = decltype(check_tag)::value;
+          const int j = j0 + kk;
+          const bool live_j = !CHECK || j < cnt;
+          const int jj = CHECK ? (live_j ? j : 0) : j;
+          const float dx = float(xi - px[jj]), dy = float(yi - py[jj]), dz = float(zi - pz[jj]);
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const float inv0 = __builtin_amdgcn_rsqf(r2);
+          const float inv = (r2 > 0.f && live_i && live_j) ? inv0 : 0.f;
+          const float inv3 = inv * inv * inv;
+          const float q0 = qs[jj][row], q1 = qs[jj][16 + row];
+          const float b0 = live_j ? q0 : 0.f;
+          const float b1 = live_j ? q1 : 0.f;
+          const float ex = dx * inv3, ey = dy * inv3, ez = dz * inv3;
+          au0 = __builtin_amdgcn_mfma_f32_16x16x4f32(inv, b0, au0, 0, 0, 0);
+          au1 = __builtin_amdgcn_mfma_f32_16x16x4f32(inv, b1, au1, 0, 0, 0);
+          ax0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, b0, ax0, 0, 0, 0);
+          ax1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ex, b1, ax1, 0, 0, 0);
+          ay0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ey, b0, ay0, 0, 0, 0);
+          ay1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ey, b1, ay1, 0, 0, 0);
+          az0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ez, b0, az0, 0, 0, 0);
+          az1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ez, b1, az1, 0, 0, 0);
+        };
+        int j0 = 0;
+        for (; j0 + 16 <= cnt; j0 += 16) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) step(j0 + 4 * u, std::false_type{});
+        }
+        for (; j0 < cnt; j0 += 4) step(j0, std::true_type{});
       }
-      neumaier16(su, cu, au);
-      neumaier16(sx, cx_, ax);
-      neumaier16(sy, cy_, ay);
-      neumaier16(sz, cz_, az);
+      neumaier4(su0, cu0, au0);
+      neumaier4(sx0, cx0, ax0);
+      neumaier4(sy0, cy0, ay0);
+      neumaier4(sz0, cz0, az0);
+      neumaier4(su1, cu1, au1);
+      neumaier4(sx1, cx1, ax1);
+      neumaier4(sy1, cy1, ay1);
+      neumaier4(sz1, cz1, az1);
     }
-    floatx16 au = su + cu, ax = sx + cx_, ay = sy + cy_, az = sz + cz_;
+    const floatx4 U[2] = {su0 + cu0, su1 + cu1}, X[2] = {sx0 + cx0, sx1 + cx1},
+                  Y[2] = {sy0 + cy0, sy1 + cy1}, Z[2] = {sz0 + cz0, sz1 + cz1};
     const float c = float(kInv4Pi);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int ti = i0 + 8 * (v / 4) + 4 * kk + (v % 4);
-      if (ti < en) {
-        const int64_t o = ti;
-        potL[o * kRB + row] += -c * au[v];
-        // field = -grad u; grad of the near part is +(1/4pi) sum q d/r^3
-        fldL[(o * 3 + 0) * kRB + row] -= c * ax[v];
-        fldL[(o * 3 + 1) * kRB + row] -= c * ay[v];
-        fldL[(o * 3 + 2) * kRB + row] -= c * az[v];
+    for (int hf = 0; hf < 2; ++hf) {
+      const int col = 16 * hf + row;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ti = i0 + 4 * kk + v;
+        if (ti < en) {
+          const int64_t o = ti;
+          potL[o * kRB + col] += -c * U[hf][v];
+          // field = -grad u; grad of the near part is +(1/4pi) sum q d/r^3
+          fldL[(o * 3 + 0) * kRB + col] -= c * X[hf][v];
+          fldL[(o * 3 + 1) * kRB + col] -= c * Y[hf][v];
+          fldL[(o * 3 + 2) * kRB + col] -= c * Z[hf][v];
+        }
       }
     }
   }
@@ -370,8 +441,18 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                                                 tab, potL, fldL);
   mk.end(kStL2P, st);
   mk.begin(kStP2P, st);
-  k_bp2p<<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_start, pl->xs, pl->ys, pl->zs, qL,
-                                              Ls.p2p_ptr, Ls.p2p_src, potL, fldL);
+  {
+    const int mlc = pl->max_leaf_count;
+    const int TW = mlc > 64 ? 8 : (mlc > 32 ? 4 : (mlc > 16 ? 2 : 1));
+    auto p2p = [&](auto kern, int tw) {
+      kern<<<(unsigned)pl->nleaf, 64 * tw, 0, st>>>(pl->leaf_start, pl->xs, pl->ys, pl->zs, qL,
+                                                     Ls.p2p_ptr, Ls.p2p_src, potL, fldL);
+    };
+    if (TW == 1) p2p(k_bp2p<1>, 1);
+    else if (TW == 2) p2p(k_bp2p<2>, 2);
+    else if (TW == 4) p2p(k_bp2p<4>, 4);
+    else p2p(k_bp2p<8>, 8);
+  }
   k_bscatter<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, potL, fldL, pot, field);
   mk.end(kStP2P, st);
   FMM_HIP(hipGetLastError());

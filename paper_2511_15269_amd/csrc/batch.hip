@@ -73,6 +73,13 @@ __global__ void k_bgather(int64_t n, int R, const int32_t* __restrict__ perm,
   qL[e] = r < R ? q[(int64_t)r * n + perm[j]] : 0.f;
 }
 
+// P2M as a contraction on the matrix cores: C[k][r] = normc_k sum_p
+// R_k(y_p) q[p][r] for the 32 vectors r.  The basis values of up to 64
+// points are formed in LDS (one lane per point); then v_mfma_f32_32x32x2f32
+// takes two points per step: A = basis of 32 coefficients (rows, one tile
+// of three) x 2 points, B = charges of the 2 points x 32 vectors.
+// Accumulator register v of lane l holds coefficient row
+// 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, vector l % 32.
 template <int P>
 __global__ __launch_bounds__(64) void k_bp2m(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
@@ -82,40 +89,52 @@ __global__ __launch_bounds__(64) void k_bp2m(
     const double* __restrict__ cz, const double* __restrict__ scale,
     const float* __restrict__ tab, float* __restrict__ C) {
   constexpr int K = K_<P>::value;
-  __shared__ float B[64][K + 1];
+  constexpr int NT = (K + 31) / 32;  // coefficient tiles
+  __shared__ float B[64][NT * 32 + 1];
+  __shared__ float Q[64][kRB];  // charges of the chunk's points
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  const int r = lane % kRB, h = lane / kRB;  // vector, half of the coefficients
-  constexpr int KH = (K + 1) / 2;
+  const int col = lane % 32, kh = lane / 32;
   const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
-  float acc[KH];
+  floatx16 acc[NT];
 #pragma unroll
-  for (int k = 0; k < KH; ++k) acc[k] = 0.f;
+  for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
   for (int c0 = st; c0 < en; c0 += 64) {
     const int j = c0 + lane;
-    __syncthreads();
-    if (j < en) {
-      regular_basis<P, float>(float((xs[j] - ox) * ir), float((ys[j] - oy) * ir),
-                              float((zs[j] - oz) * ir), [&](int k, float v) { B[lane][k] = v; });
-    }
-    __syncthreads();
     const int cnt = min(64, en - c0);
-    for (int i = 0; i < cnt; ++i) {
-      const float qi = qL[(int64_t)(c0 + i) * kRB + r];
+    __syncthreads();
+    {
+      // padding rows and missing points read as zero
+      const bool pt = j < en;
+      const int jj = pt ? j : c0;
 #pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int kk = h * KH + k;
-        if (kk < K) acc[k] = fma(qi, B[i][kk], acc[k]);
-      }
+      for (int k = K; k < NT * 32; ++k) B[lane][k] = 0.f;
+      regular_basis<P, float>(float((xs[jj] - ox) * ir), float((ys[jj] - oy) * ir),
+                              float((zs[jj] - oz) * ir),
+                              [&](int k, float v) { B[lane][k] = pt ? v : 0.f; });
+      const float4* from = reinterpret_cast<const float4*>(qL + (int64_t)c0 * kRB);
+      for (int e = lane; e < cnt * (kRB / 4); e += 64)
+        reinterpret_cast<float4*>(&Q[0][0])[e] = from[e];
+    }
+    __syncthreads();
+    for (int p0 = 0; p0 < cnt; p0 += 2) {
+      const int pp = p0 + kh;
+      const float b = pp < cnt ? Q[pp][col] : 0.f;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(B[pp < 64 ? pp : 0][t * 32 + col], b, acc[t],
+                                                      0, 0, 0);
     }
   }
 #pragma unroll
-  for (int k = 0; k < KH; ++k) {
-    const int kk = h * KH + k;
-    if (kk < K) C[(g * K + kk) * kRB + r] = acc[k] * tab[tab_normc(P) + kk];
-  }
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int k = t * 32 + 8 * (v / 4) + 4 * kh + v % 4;
+      if (k < K) C[(g * K + k) * kRB + col] = acc[t][v] * tab[tab_normc(P) + k];
+    }
 }
 
 // parent += M2M(child) over the 2^s children; one (parent, vector) per lane
@@ -201,7 +220,13 @@ __global__ __launch_bounds__(64) void k_bl2l(
   for (int k = 0; k < K; ++k) D[(t * K + k) * kRB + r] = D[(t * K + k) * kRB + r] + v[k];
 }
 
-// L2P for 32 points at a time: basis and gradient in LDS, lane r sums.
+// L2P as a contraction on the matrix cores: for 32 points at a time,
+// u[p][r] = sum_k R_k(y_p) w_k D[k][r] and likewise the three gradient
+// components.  The basis and its gradient are formed in LDS (one lane per
+// point); v_mfma_f32_32x32x2f32 then takes two coefficients per step:
+// A = basis values of 32 points (rows) x 2 coefficients, B = weighted local
+// coefficients (2 x 32 vectors).  Accumulator register v of lane l holds
+// point row 8 (v / 4) + 4 (l / 32) + v % 4, vector l % 32.
 template <int P>
 __global__ __launch_bounds__(64) void k_bl2p(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
@@ -211,47 +236,55 @@ __global__ __launch_bounds__(64) void k_bl2p(
     const double* __restrict__ scale, const float* __restrict__ D,
     const float* __restrict__ tab, float* __restrict__ potL, float* __restrict__ fldL) {
   constexpr int K = K_<P>::value;
+  constexpr int K2 = (K + 1) / 2 * 2;  // coefficient pairs (one zero row padded)
   constexpr int NP = 32;
-  __shared__ float Bv[NP][4][K];
+  __shared__ float Bv[4][K2][NP + 1];
   const int leaf = blockIdx.x;
   const int lane = threadIdx.x;
-  const int r = lane % kRB, h = lane / kRB;
+  const int col = lane % 32, kh = lane / 32;
   const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   const float fu = float(-kInv4Pi * ir), ff = float(kInv4Pi * ir * ir);
-  float w[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) w[k] = D[(g * K + k) * kRB + r] * tab[tab_l2p(P) + k];
   for (int c0 = st; c0 < en; c0 += NP) {
+    const int cnt = min(NP, en - c0);
     __syncthreads();
-    if (lane < NP && c0 + lane < en) {
-      const int j = c0 + lane;
+    if (lane < NP) {
+      const bool pt = lane < cnt;
+      const int j = pt ? c0 + lane : c0;
       const float x = float((xs[j] - ox) * ir), y = float((ys[j] - oy) * ir),
                   z = float((zs[j] - oz) * ir);
       basis_with_gradient<P, float>(x, y, z, [&](int k, float v, float gx, float gy, float gz) {
-        Bv[lane][0][k] = v;
-        Bv[lane][1][k] = gx;
-        Bv[lane][2][k] = gy;
-        Bv[lane][3][k] = gz;
+        Bv[0][k][lane] = pt ? v : 0.f;
+        Bv[1][k][lane] = pt ? gx : 0.f;
+        Bv[2][k][lane] = pt ? gy : 0.f;
+        Bv[3][k][lane] = pt ? gz : 0.f;
       });
+      if (K2 > K) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Bv[c][K2 - 1][lane] = 0.f;
+      }
     }
     __syncthreads();
-    const int cnt = min(NP, en - c0);
-    for (int i = h; i < cnt; i += 2) {
-      float u = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+    floatx16 au = {}, ax = {}, ay = {}, az = {};
+    for (int k0 = 0; k0 < K2; k0 += 2) {
+      const int k = k0 + kh;
+      const float b = k < K ? D[(g * K + k) * kRB + col] * tab[tab_l2p(P) + k] : 0.f;
+      au = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[0][k][col], b, au, 0, 0, 0);
+      ax = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[1][k][col], b, ax, 0, 0, 0);
+      ay = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[2][k][col], b, ay, 0, 0, 0);
+      az = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[3][k][col], b, az, 0, 0, 0);
+    }
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        u = fma(w[k], Bv[i][0][k], u);
-        gx = fma(w[k], Bv[i][1][k], gx);
-        gy = fma(w[k], Bv[i][2][k], gy);
-        gz = fma(w[k], Bv[i][3][k], gz);
+    for (int v = 0; v < 16; ++v) {
+      const int pnt = 8 * (v / 4) + 4 * kh + v % 4;
+      if (pnt < cnt) {
+        const int64_t o = c0 + pnt;
+        potL[o * kRB + col] = fu * au[v];
+        fldL[(o * 3 + 0) * kRB + col] = ff * ax[v];
+        fldL[(o * 3 + 1) * kRB + col] = ff * ay[v];
+        fldL[(o * 3 + 2) * kRB + col] = ff * az[v];
       }
-      const int64_t o = c0 + i;
-      potL[o * kRB + r] = fu * u;
-      fldL[(o * 3 + 0) * kRB + r] = ff * gx;
-      fldL[(o * 3 + 1) * kRB + r] = ff * gy;
-      fldL[(o * 3 + 2) * kRB + r] = ff * gz;
     }
   }
 }

@@ -171,6 +171,7 @@ def main():
         return e0.elapsed_time(e1) / steps
 
     res_variants = {}
+    res_tiles = {}
 
     def run_forward(prec, profile):
         plan, plan_ms = build(prec)
@@ -178,6 +179,8 @@ def main():
         qd = q64.to(tdt)
         pot = torch.empty((1, args.n), dtype=tdt, device=dev)
         fld = torch.empty((1, args.n, 3), dtype=tdt, device=dev)
+        tiles = plan.autotune(qd[0] if qd.dim() > 1 else qd)
+        res_tiles[prec] = tiles
         fn = lambda: plan.evaluate(qd, out=(pot, fld))
         for _ in range(args.warmup):
             fn()
@@ -290,7 +293,8 @@ def main():
                                f"leaf<={args.leaf}, s={args.splits}, theta={args.theta}, "
                                f"potential+field, {head} forward pass on a cached plan",
                    "n": args.n, "p": args.p, "leaf_max": args.leaf, "splits": args.splits,
-                   "theta": args.theta, "precision": head},
+                   "theta": args.theta, "precision": head,
+                   "tiles": res_tiles.get(head)},
         "accuracy": {**acc, "targets": len(tg), "reference": "direct sum (FP64), library kernel"},
         "variants": res_variants,
         "stage_ms": per_stage,

@@ -219,6 +219,20 @@ fmm_status fmm_plan_set_profiling(fmm_plan* plan, int enable);
 fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
                                  int64_t* passes);
 
+/* Choose the launch tiles of the single-vector evaluation by timing them
+ * on this plan: the number of source groups of the near-field kernel
+ * (1, 2 or 4) and the number of leaves per wave of P2M and L2P (1, 2, 4 or
+ * 8), among the values the plan's largest leaf allows.  Every candidate
+ * runs one untimed and three timed evaluations of the charges q (device,
+ * [n], the plan's precision) on `stream`; the fastest pair is stored in the
+ * plan and used by every later evaluation (results change only by the
+ * summation order inside the near field and the multipole sums).  The
+ * chosen values are written to *p2p_groups and *leaves_per_wave (host; may
+ * be NULL).  Synchronises `stream`; allocates and frees temporary output
+ * buffers.  Errors: FMM_EINVAL (NULL plan or q), FMM_ENOMEM, FMM_EDEVICE. */
+fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p2p_groups,
+                             int* leaves_per_wave);
+
 /* Release the plan and its device memory (NULL is accepted). */
 fmm_status fmm_plan_destroy(fmm_plan* plan);
 

@@ -182,6 +182,18 @@ class Plan:
             return pot[0], (fld[0] if fld is not None else None)
         return pot, fld
 
+    def autotune(self, q: torch.Tensor, stream=None) -> dict:
+        """Time the near-field source groups and the P2M/L2P leaves per wave
+        on charges ``q`` ([N], CUDA, plan precision) and keep the fastest
+        (fmm_plan_autotune).  Returns the chosen values."""
+        qq = self._vec(q, "q")
+        g, lw = ctypes.c_int(), ctypes.c_int()
+        with torch.cuda.device(self.device):
+            check(lib().fmm_plan_autotune(self._h, ctypes.c_void_p(qq.data_ptr()),
+                                          _stream_ptr(stream), ctypes.byref(g),
+                                          ctypes.byref(lw)))
+        return {"p2p_groups": g.value, "leaves_per_wave": lw.value}
+
     def set_profiling(self, on: bool = True) -> None:
         """Record per-stage HIP events in every evaluate (see
         read_profile)."""

@@ -68,11 +68,14 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(vp)]
         L.fmm_graph_launch.argtypes = [vp, vp]
         L.fmm_graph_destroy.argtypes = [vp]
+        L.fmm_plan_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]
         for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
                   "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy",
                   "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile",
                   "fmm_evaluate_transposed", "fmm_adjoint", "fmm_multi_plan_create",
-                  "fmm_graph_create", "fmm_graph_launch", "fmm_graph_destroy"):
+                  "fmm_graph_create", "fmm_graph_launch", "fmm_graph_destroy",
+                  "fmm_plan_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -591,6 +591,67 @@ fmm_status fmm_graph_destroy(fmm_graph* g) {
   });
 }
 
+fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* groups_out,
+                             int* leaves_out) {
+  return guard([&] {
+    if (!pl || !q) throw Error{FMM_EINVAL, "plan and q must not be NULL"};
+    check_device(pl);
+    const hipStream_t st = (hipStream_t)stream;
+    const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+    void* pot = nullptr;
+    void* fld = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = pl->profiling;
+    const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave;
+    auto cleanup = [&] {
+      if (pot) (void)hipFree(pot);
+      if (fld) (void)hipFree(fld);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      pl->profiling = prof;
+    };
+    try {
+      FMM_HIP(hipMalloc(&pot, es * (size_t)pl->n));
+      FMM_HIP(hipMalloc(&fld, es * 3 * (size_t)pl->n));
+      FMM_HIP(hipEventCreate(&e0));
+      FMM_HIP(hipEventCreate(&e1));
+      pl->profiling = false;
+      float best = -1.f;
+      int bg = 0, bl = 0;
+      for (int g : {1, 2, 4}) {
+        if (!valid_p2p_groups(pl, g)) continue;
+        for (int l : {1, 2, 4, 8}) {
+          if (!valid_leaves_per_wave(pl, l)) continue;
+          pl->p2p_groups = g;
+          pl->leaves_per_wave = l;
+          fmm::evaluate(pl, 0, q, 1, pot, fld, st);
+          FMM_HIP(hipEventRecord(e0, st));
+          for (int r = 0; r < 3; ++r) fmm::evaluate(pl, 0, q, 1, pot, fld, st);
+          FMM_HIP(hipEventRecord(e1, st));
+          FMM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          FMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (best < 0.f || ms < best) {
+            best = ms;
+            bg = g;
+            bl = l;
+          }
+        }
+      }
+      pl->p2p_groups = bg;
+      pl->leaves_per_wave = bl;
+    } catch (...) {
+      pl->p2p_groups = g0;
+      pl->leaves_per_wave = l0;
+      cleanup();
+      throw;
+    }
+    cleanup();
+    if (groups_out) *groups_out = pl->p2p_groups;
+    if (leaves_out) *leaves_out = pl->leaves_per_wave;
+  });
+}
+
 fmm_status fmm_plan_destroy(fmm_plan* pl) {
   return guard([&] {
     if (!pl) return;

@@ -432,7 +432,8 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   // far field
   // leaves per wave for P2M and L2P: every lane holds at most one point
   const int mlc = pl->max_leaf_count;
-  const int GL = mlc > 32 ? 1 : (mlc > 16 ? 2 : (mlc > 8 ? 4 : 8));
+  (void)mlc;
+  const int GL = leaves_per_wave(pl);
   const int64_t nl = pl->nleaf;
   const unsigned nb_l = (unsigned)((nl + GL - 1) / GL);
   mk.begin(kStP2M, st);
@@ -468,7 +469,7 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.end(kStL2L, st);
   // near field
   mk.begin(kStP2P, st);
-  const int G = pl->max_leaf_count > 32 ? 1 : (pl->max_leaf_count > 16 ? 2 : 4);
+  const int G = p2p_groups(pl);
   auto p2p = [&](auto kern) {
     kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(n, pl->leaf_start, src, Ls.p2p_ptr, Ls.p2p_src,
                                               pl->has_dup ? 1 : 0, near);
@@ -503,6 +504,28 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.end(kStL2P, st);
   FMM_HIP(hipGetLastError());
 }
+
+}  // namespace
+
+bool valid_p2p_groups(const fmm_plan* pl, int g) {
+  return g == 1 || ((g == 2 || g == 4) && pl->max_leaf_count <= 64 / g);
+}
+bool valid_leaves_per_wave(const fmm_plan* pl, int l) {
+  return l == 1 || ((l == 2 || l == 4 || l == 8) && pl->max_leaf_count <= 64 / l);
+}
+int p2p_groups(const fmm_plan* pl) {
+  if (pl->p2p_groups && valid_p2p_groups(pl, pl->p2p_groups)) return pl->p2p_groups;
+  const int m = pl->max_leaf_count;
+  return m > 32 ? 1 : (m > 16 ? 2 : 4);
+}
+int leaves_per_wave(const fmm_plan* pl) {
+  if (pl->leaves_per_wave && valid_leaves_per_wave(pl, pl->leaves_per_wave))
+    return pl->leaves_per_wave;
+  const int m = pl->max_leaf_count;
+  return m > 32 ? 1 : (m > 16 ? 2 : (m > 8 ? 4 : 8));
+}
+
+namespace {
 
 template <typename T>
 void dispatch(int p, fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field,

@@ -93,6 +93,10 @@ struct fmm_plan {
   double* scale = nullptr;   // [nbox] length scale of the box's expansions
   int32_t max_leaf_count = 0;
   bool has_dup = true;  // some two points coincide (set by the tree build)
+  // launch tiles (0: the default rule from max_leaf_count; set by
+  // fmm_plan_autotune): P2P source groups, P2M/L2P leaves per wave
+  int p2p_groups = 0;
+  int leaves_per_wave = 0;
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   std::vector<fmm::Step> m2m_steps;  // bottom-up, parents of one level per step
   std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level with a parent local
@@ -178,6 +182,14 @@ void adjoint_combine(fmm_plan* pl, const void* q, const void* g, const void* fie
 void direct_sum(int64_t n, const double* pos, const void* q, int precision,
                 const int64_t* targets, int64_t nt, void* pot, void* field,
                 hipStream_t st);
+// Launch tiles in effect (eval.hip): P2P source groups G (1, 2, 4; G > 1
+// needs max_leaf_count <= 64 / G) and P2M/L2P leaves per wave (1, 2, 4, 8;
+// needs max_leaf_count <= 64 / leaves).
+int p2p_groups(const fmm_plan* pl);
+int leaves_per_wave(const fmm_plan* pl);
+bool valid_p2p_groups(const fmm_plan* pl, int g);
+bool valid_leaves_per_wave(const fmm_plan* pl, int l);
+
 // Stage-timing helpers (api.cpp).
 hipEvent_t take_event(fmm_plan* pl);
 void release_profile(fmm_plan* pl);

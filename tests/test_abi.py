@@ -101,3 +101,8 @@ def test_graph_null_arguments():
     assert lib.fmm_graph_launch(None, None) == L.FMM_EINVAL
     assert lib.fmm_graph_destroy(None) == L.FMM_OK
     assert lib.fmm_multi_plan_create(None, None, 1, None, None, ctypes.byref(out)) == L.FMM_EINVAL
+
+
+def test_autotune_null_arguments():
+    lib = L.lib()
+    assert lib.fmm_plan_autotune(None, None, None, None, None) == L.FMM_EINVAL

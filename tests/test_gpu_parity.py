@@ -484,3 +484,24 @@ def test_graph_replays_match_eager_runs(fmm, prec, sizes, n, R, transposed):
         torch.cuda.synchronize()
         _say(f"    replay {rep}")
         assert torch.equal(g.pot, u) and torch.equal(g.field, f)
+
+
+@pytest.mark.parametrize("prec,n,leaf,s,tol", [("fp64", 30000, 64, 2, 1e-12),
+                                               ("fp32", 20000, 128, 3, 1e-6)])
+def test_autotuned_tiles_give_the_same_results(fmm, prec, n, leaf, s, tol):
+    """Tiles chosen by timing change only summation orders: results equal
+    the default tiles' to rounding, and stay within the oracle bound."""
+    _say(f"[autotune] {prec} n={n} leaf={leaf} s={s}")
+    pos, q = workloads.uniform_cube(n, 80)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda().to(dt)
+    a = fmm.Plan(pt, p=6, leaf_max=leaf, splits=s, theta=0.7, precision=prec)
+    b = fmm.Plan(pt, p=6, leaf_max=leaf, splits=s, theta=0.7, precision=prec)
+    choice = b.autotune(qt)
+    _say(f"    chosen {choice}")
+    assert choice["p2p_groups"] in (1, 2, 4) and choice["leaves_per_wave"] in (1, 2, 4, 8)
+    ua, fa = a.evaluate(qt)
+    ub, fb = b.evaluate(qt)
+    assert _rel(ub.double().cpu().numpy(), ua.double().cpu().numpy()) <= tol
+    assert _rel(fb.double().cpu().numpy(), fa.double().cpu().numpy()) <= tol

@@ -333,9 +333,10 @@ __device__ __forceinline__ void regular_basis(T x, T y, T z, F&& f) {
 
 // Regular basis R-hat^m_n and its gradient (App. A.1, A.3; the sectoral
 // gradient without the printed leading minus) in order-major sweeps; calls
-// f(k, value, d/dx, d/dy, d/dz) once per coefficient index k.
-template <int P, typename T, typename F>
-__device__ __forceinline__ void basis_with_gradient(T x, T y, T z, F&& f) {
+// f(k, value, d/dx, d/dy, d/dz) once per coefficient index k and
+// band_end() after the last coefficient of every order m.
+template <int P, typename T, typename F, typename E>
+__device__ __forceinline__ void basis_with_gradient(T x, T y, T z, F&& f, E&& band_end) {
   const T r2 = x * x + y * y + z * z;
   // sectoral value and gradient (z component of a sectoral gradient is 0)
   T sc = T(1), ss = T(0), scx = T(0), scy = T(0), ssx = T(0), ssy = T(0);
@@ -392,20 +393,60 @@ __device__ __forceinline__ void basis_with_gradient(T x, T y, T z, F&& f) {
       c1 = c; c1x = cxg; c1y = cyg; c1z = czg;
       s1 = s; s1x = sxg; s1y = syg; s1z = szg;
     }
+    band_end();
   }
 }
 
-// pot += sum_k w[k] R-hat_k, grad += sum_k w[k] grad R-hat_k
+template <int P, typename T, typename F>
+__device__ __forceinline__ void basis_with_gradient(T x, T y, T z, F&& f) {
+  basis_with_gradient<P, T>(x, y, z, f, [] {});
+}
+
+// Neumaier's compensated addition: s + c carries the running sum.
+template <typename T>
+__device__ __forceinline__ void neumaier(T& s, T& c, T x) {
+  const T t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+// pot += sum_k w[k] R-hat_k, grad += sum_k w[k] grad R-hat_k.  In FP32 the
+// terms of each order m are summed on their own and the order sums are
+// added with Neumaier compensation.
 template <int P, typename T>
 __device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ w,
                                            T& pot, T& gx, T& gy, T& gz) {
-  basis_with_gradient<P, T>(x, y, z, [&](int k, T v, T dx, T dy, T dz) {
-    const T wk = w[k];
-    pot = fma(wk, v, pot);
-    gx = fma(wk, dx, gx);
-    gy = fma(wk, dy, gy);
-    gz = fma(wk, dz, gz);
-  });
+  constexpr bool kComp = sizeof(T) == 4;
+  T bp = T(0), bx = T(0), by = T(0), bz = T(0);
+  T cp = T(0), cx = T(0), cy = T(0), cz = T(0);
+  T& ap = kComp ? bp : pot;
+  T& ax = kComp ? bx : gx;
+  T& ay = kComp ? by : gy;
+  T& az = kComp ? bz : gz;
+  basis_with_gradient<P, T>(
+      x, y, z,
+      [&](int k, T v, T dx, T dy, T dz) {
+        const T wk = w[k];
+        ap = fma(wk, v, ap);
+        ax = fma(wk, dx, ax);
+        ay = fma(wk, dy, ay);
+        az = fma(wk, dz, az);
+      },
+      [&] {
+        if (kComp) {
+          neumaier(pot, cp, bp);
+          neumaier(gx, cx, bx);
+          neumaier(gy, cy, by);
+          neumaier(gz, cz, bz);
+          bp = bx = by = bz = T(0);
+        }
+      });
+  if (kComp) {
+    pot += cp;
+    gx += cx;
+    gy += cy;
+    gz += cz;
+  }
 }
 
 // ---------------------------------------------------------------- P2P
@@ -476,13 +517,6 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// Neumaier's compensated addition: s + c carries the running sum.
-template <typename T>
-__device__ __forceinline__ void neumaier(T& s, T& c, T x) {
-  const T t = s + x;
-  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-  s = t;
-}
 
 
 }  // namespace ops

@@ -247,6 +247,8 @@ def main():
     if not args.only_headline and not args.no_batched:
         res_variants.update(run_batched(F, torch, dev, args, timed, rel))
         res_variants.update(run_uneven(F, torch, dev, args, timed, rel))
+    if not args.only_headline:
+        res_variants.update(run_paper_sets(F, torch, dev, pos_d, q64, timed))
 
     # roofline of the dominant kernel of the headline pass (one launch per pass)
     dom = max(per_stage, key=per_stage.get)
@@ -342,6 +344,35 @@ def run_batched(F, torch, dev, args, timed, rel, n=1 << 18, R=32):
     }
     log(f"batched {R}x{n} fp32: {ms_b:.3f} ms ({R * n / ms_b / 1e3:.1f} Mpoints/s); "
         f"{R} single passes {ms_s:.3f} ms ({R * n / ms_s / 1e3:.1f}); {acc}")
+    return out
+
+
+def run_paper_sets(F, torch, dev, pos_d, q64, timed):
+    """The paper's own timed setting on the same 2^20-point uniform cube:
+    potential only, relative L-infinity error against the direct sum, its
+    three parameter sets (Sec. III.A, Tables II-III; s = 2).  Context for
+    the paper's single-GPU figures, not the headline metric."""
+    sets = {"paper_set1": (5, 0.70, 128, "fp32"), "paper_set2": (9, 0.50, 256, "fp32"),
+            "paper_set3": (10, 0.27, 256, "fp64")}
+    ud, _ = F.direct(pos_d, q64, field=False)
+    ud = ud.cpu().numpy()
+    n = len(ud)
+    out = {}
+    for name, (p, th, leaf, prec) in sets.items():
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        plan = F.Plan(pos_d, p=p, leaf_max=leaf, splits=2, theta=th, precision=prec)
+        qd = q64.to(dt).reshape(1, n)
+        plan.autotune(qd[0])
+        pot = torch.empty((1, n), dtype=dt, device=dev)
+        ms = timed(lambda: plan.evaluate(qd, field=False, out=(pot, None)), 10, 2)
+        u = pot[0].double().cpu().numpy()
+        linf = float(np.abs(u - ud).max() / np.abs(ud).max())
+        out[name] = {"p": p, "theta": th, "leaf_max": leaf, "splits": 2, "precision": prec,
+                     "output": "potential", "ms_per_step": ms, "mpoints_s": n / ms / 1e3,
+                     "rel_linf_pot": linf}
+        log(f"{name} (p={p}, theta={th}, leaf<={leaf}, s=2, {prec}, potential only): "
+            f"{ms:.3f} ms ({n / ms / 1e3:.1f} Mpoints/s), rel L-inf {linf:.2e}")
+        del plan
     return out
 
 

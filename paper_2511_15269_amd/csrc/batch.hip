@@ -64,15 +64,6 @@ __device__ __forceinline__ void neumaier16(floatx16& s, floatx16& c, floatx16 x)
 }
 
 // charges to leaf order, vectors innermost (zero past the last vector)
-__global__ void k_bgather(int64_t n, int R, const int32_t* __restrict__ perm,
-                          const float* __restrict__ q, float* __restrict__ qL) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * kRB) return;
-  const int64_t j = e / kRB;
-  const int r = (int)(e - j * kRB);
-  qL[e] = r < R ? q[(int64_t)r * n + perm[j]] : 0.f;
-}
-
 // P2M as a contraction on the matrix cores: C[k][r] = normc_k sum_p
 // R_k(y_p) q[p][r] for the 32 vectors r.  The basis values of up to 64
 // points are formed in LDS (one lane per point); then v_mfma_f32_32x32x2f32
@@ -80,11 +71,15 @@ __global__ void k_bgather(int64_t n, int R, const int32_t* __restrict__ perm,
 // of three) x 2 points, B = charges of the 2 points x 32 vectors.
 // Accumulator register v of lane l holds coefficient row
 // 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, vector l % 32.
+// The kernel also does the sort stage: it gathers the charges of the leaf's
+// points from the caller's layout (vector-major, input order) and writes
+// them leaf-ordered, 32 vectors innermost and zero beyond R, for P2P.
 template <int P>
 __global__ __launch_bounds__(64) void k_bp2m(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
-    const double* __restrict__ zs, const float* __restrict__ qL,
+    const double* __restrict__ zs, int64_t n, int R, const int32_t* __restrict__ perm,
+    const float* __restrict__ q, float* __restrict__ qL,
     const double* __restrict__ cx, const double* __restrict__ cy,
     const double* __restrict__ cz, const double* __restrict__ scale,
     const float* __restrict__ tab, float* __restrict__ C) {
@@ -114,9 +109,12 @@ __global__ __launch_bounds__(64) void k_bp2m(
       regular_basis<P, float>(float((xs[jj] - ox) * ir), float((ys[jj] - oy) * ir),
                               float((zs[jj] - oz) * ir),
                               [&](int k, float v) { B[lane][k] = pt ? v : 0.f; });
-      const float4* from = reinterpret_cast<const float4*>(qL + (int64_t)c0 * kRB);
-      for (int e = lane; e < cnt * (kRB / 4); e += 64)
-        reinterpret_cast<float4*>(&Q[0][0])[e] = from[e];
+      for (int e = lane; e < cnt * kRB; e += 64) {
+        const int pj = e / kRB, r = e % kRB;
+        const float v = r < R ? q[(int64_t)r * n + perm[c0 + pj]] : 0.f;
+        Q[pj][r] = v;
+        qL[(int64_t)c0 * kRB + e] = v;
+      }
     }
     __syncthreads();
     for (int p0 = 0; p0 < cnt; p0 += 2) {
@@ -441,12 +439,12 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   float* fldL = (float*)pl->bfld;
   const int64_t n = pl->n;
   StageMarks mk(pl);
+  // the sort stage is folded into P2M; its timing slot stays empty
   mk.begin(kStSort, st);
-  k_bgather<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, q, qL);
   mk.end(kStSort, st);
   mk.begin(kStP2M, st);
   k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
-                                                pl->zs, qL, pl->cx, pl->cy, pl->cz, pl->scale,
+                                                pl->zs, n, R, pl->perm, q, qL, pl->cx, pl->cy, pl->cz, pl->scale,
                                                 tab, C);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);

@@ -49,15 +49,18 @@ constexpr int kM2LThreads = 64;
 // ---------------------------------------------------------------- P2M
 // C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole).
 // G leaves per wave (LW = 64/G lanes each, lane = point); the per-lane sums
-// are combined by a butterfly over the leaf's lanes.
+// are combined by a butterfly over the leaf's lanes.  The kernel also does
+// the sort stage: it reads each charge in input order and writes the leaf's
+// 32-byte source records that P2P reads.
 template <int P, typename T, int G>
 __global__ __launch_bounds__(64) void k_p2m(
     int64_t nleaf, const int32_t* __restrict__ leaf_box,
     const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs,
-    const Src<T>* __restrict__ src, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
-    const double* __restrict__ scale, const T* __restrict__ tab, T* __restrict__ C) {
+    const int32_t* __restrict__ perm, const T* __restrict__ q, Src<T>* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ tab, T* __restrict__ C) {
   constexpr int K = K_<P>::value;
   constexpr int LW = 64 / G;
   __shared__ T cs[G][K];  // finished sums, stored coalesced at the end
@@ -72,8 +75,9 @@ __global__ __launch_bounds__(64) void k_p2m(
     // at most one point per lane: reduce every coefficient as it is formed
     const int j = st + l;
     const bool pt = j < en;
-    const T qj = pt ? src[j].q : T(0);
     const int jj = pt ? j : st;
+    const T qj = pt ? q[perm[j]] : T(0);
+    if (pt) src[j] = Src<T>{xs[j], ys[j], zs[j], qj};
     regular_basis<P, T>(T((xs[jj] - ox) * ir), T((ys[jj] - oy) * ir), T((zs[jj] - oz) * ir),
                         [&](int k, T v) {
                           const T sum = group_sum<LW>(qj * v);
@@ -84,7 +88,8 @@ __global__ __launch_bounds__(64) void k_p2m(
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = T(0);
     for (int j = st + l; j < en; j += LW) {
-      const T qj = src[j].q;
+      const T qj = q[perm[j]];
+      src[j] = Src<T>{xs[j], ys[j], zs[j], qj};
       regular_basis<P, T>(T((xs[j] - ox) * ir), T((ys[j] - oy) * ir), T((zs[j] - oz) * ir),
                           [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
     }
@@ -386,16 +391,6 @@ __global__ __launch_bounds__(64) void k_p2p(
   }
 }
 
-// sort stage: source records in leaf order with their charges
-template <typename T>
-__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm,
-                         const double* __restrict__ xs, const double* __restrict__ ys,
-                         const double* __restrict__ zs, const T* __restrict__ q,
-                         Src<T>* __restrict__ src) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) src[j] = Src<T>{xs[j], ys[j], zs[j], q[perm[j]]};
-}
-
 // d/dx_k of sum_i g_i u_i: g_k grad u(x_k) (x_k as a target of the forward
 // pass) + q_k grad v(x_k) (x_k as a source, v = transposed pass with charges
 // g); fields are -grad.
@@ -426,20 +421,19 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   T* near = (T*)pl->near;
   const int64_t n = pl->n;
   StageMarks mk(pl);
+  // the sort stage (charges into leaf-ordered source records) is folded
+  // into P2M; its timing slot stays empty
   mk.begin(kStSort, st);
-  k_gather<T><<<blocks(n, 256), 256, 0, st>>>(n, pl->perm, pl->xs, pl->ys, pl->zs, q, src);
   mk.end(kStSort, st);
   // far field
   // leaves per wave for P2M and L2P: every lane holds at most one point
-  const int mlc = pl->max_leaf_count;
-  (void)mlc;
   const int GL = leaves_per_wave(pl);
   const int64_t nl = pl->nleaf;
   const unsigned nb_l = (unsigned)((nl + GL - 1) / GL);
   mk.begin(kStP2M, st);
   auto p2m = [&](auto kern) {
-    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs, src,
-                              pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs,
+                              pl->perm, q, src, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
   };
   if (GL == 1) p2m(k_p2m<P, T, 1>);
   else if (GL == 2) p2m(k_p2m<P, T, 2>);

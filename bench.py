@@ -63,14 +63,15 @@ def traffic_from_profile(kernel_prefix: str, tag: str):
     return float(t.group(1))
 
 
-KERNEL_SOURCES = ("eval.hip", "ops.h", "tables.h", "tables.cpp")
+KERNEL_SOURCES = ("csrc/eval.hip", "csrc/ops.h", "csrc/tables.h", "csrc/tables.cpp", "build.py")
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the sources of the single-vector evaluation kernels."""
+    """sha256 over the sources and build flags of the single-vector
+    evaluation kernels."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2511_15269_amd", "csrc", f), "rb").read())
+        h.update(open(os.path.join(ROOT, "paper_2511_15269_amd", f), "rb").read())
     return h.hexdigest()
 
 

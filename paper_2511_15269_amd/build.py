@@ -22,7 +22,12 @@ SOURCES = ["api.cpp", "tables.cpp", "sort.hip", "tree.hip", "lists.hip", "direct
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(os.path.dirname(PKG), "include")]
-DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The translation kernels rely on fully unrolled coefficient loops (a rolled
+# loop indexes the per-lane coefficient arrays at run time and moves them to
+# scratch memory); the default size limit of the unroll pragma stops short of
+# that for some expansion orders (p = 6, 7), so it is raised.
+DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-pragma-unroll-threshold=200000"]
 
 
 def _compile(src: str) -> str:

@@ -209,6 +209,8 @@ fmm_status fmm_direct(const double* pos, int64_t n, const void* q, int precision
  * (Sec. III.A: sort, mpls, M2M, M2L, L2L, evloc, evdir).  Stage indices:
  *   0 sort (charges to leaf order), 1 P2M, 2 M2M, 3 M2L, 4 L2L,
  *   5 L2P (evloc), 6 P2P (evdir).
+ * The P2M kernels also do the sort stage, so its time is counted under
+ * P2M and stage 0 holds only the cost of its pair of events.
  * While enabled, every evaluation records a HIP event before and after each
  * stage on its stream.  fmm_plan_read_profile waits for those
  * events, writes the summed milliseconds per stage to

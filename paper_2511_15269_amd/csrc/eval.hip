@@ -455,8 +455,8 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
   if (pl->l2l_sum.n > 0)
-    k_psum<T><<<(unsigned)pl->l2l_sum.n, 64, 0, st>>>(pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr,
-                                                      part, K_<P>::value, D);
+    k_psum<T><<<(unsigned)pl->l2l_sum.n, K_<P>::value <= 64 ? 64 : 128, 0, st>>>(
+        pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr, part, K_<P>::value, D);
   for (const Step& S : pl->l2l_steps)
     k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz,
                                                 pl->scale, tab, D);

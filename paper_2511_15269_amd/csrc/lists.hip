@@ -151,10 +151,13 @@ void keys_to_csr(fmm_plan* pl, Scratch& sc, uint64_t* keys, int64_t nk,
   FMM_HIP(hipGetLastError());
 }
 
-// M2L work items of a list set: at most kItemPairs pairs each, consecutive
-// per target.
+// M2L work items of a list set: consecutive per target, each target's list
+// split into ceil(len / kItemPairs) items of equal length (+-1).  Shorter
+// items give more, more even work units (M2L runs one wave per SIMD, so the
+// last round of waves is what items of 16 leave unbalanced) at the price of
+// more partial rows for the sum before L2L; 12 measured best.
 void make_items(fmm_plan* pl, ListSet& S, hipStream_t st) {
-  const int kItemPairs = 16;
+  const int kItemPairs = 12;
   std::vector<int32_t> mptr(pl->nbox + 1);
   FMM_HIP(hipMemcpyAsync(mptr.data(), S.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
                          hipMemcpyDeviceToHost, st));
@@ -162,10 +165,12 @@ void make_items(fmm_plan* pl, ListSet& S, hipStream_t st) {
   std::vector<int32_t> it_t, it_b, it_e, it_ptr(pl->nbox + 1);
   for (int64_t t = 0; t < pl->nbox; ++t) {
     it_ptr[t] = (int32_t)it_t.size();
-    for (int32_t b = mptr[t]; b < mptr[t + 1]; b += kItemPairs) {
+    const int32_t lt = mptr[t + 1] - mptr[t];
+    const int32_t ni = (lt + kItemPairs - 1) / kItemPairs;
+    for (int32_t j = 0; j < ni; ++j) {
       it_t.push_back((int32_t)t);
-      it_b.push_back(b);
-      it_e.push_back(std::min(b + kItemPairs, mptr[t + 1]));
+      it_b.push_back(mptr[t] + (int32_t)((int64_t)lt * j / ni));
+      it_e.push_back(mptr[t] + (int32_t)((int64_t)lt * (j + 1) / ni));
     }
   }
   it_ptr[pl->nbox] = (int32_t)it_t.size();

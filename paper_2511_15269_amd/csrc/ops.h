@@ -470,7 +470,17 @@ __global__ void k_psum(int64_t nb, const int32_t* __restrict__ boxes,
   const int b = item_ptr[t], e = item_ptr[t + 1];
   for (int k = threadIdx.x; k < W; k += blockDim.x) {
     T acc = T(0);
-    for (int it = b; it < e; ++it) acc += partial[(int64_t)it * W + k];
+    int it = b;
+    // four rows' loads in flight at a time; the sum keeps item order
+    for (; it + 4 <= e; it += 4) {
+      const T r0 = partial[(int64_t)it * W + k], r1 = partial[(int64_t)(it + 1) * W + k];
+      const T r2 = partial[(int64_t)(it + 2) * W + k], r3 = partial[(int64_t)(it + 3) * W + k];
+      acc += r0;
+      acc += r1;
+      acc += r2;
+      acc += r3;
+    }
+    for (; it < e; ++it) acc += partial[(int64_t)it * W + k];
     D[t * W + k] = acc;
   }
 }

@@ -11,6 +11,7 @@ calls raise.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -23,27 +24,54 @@ __all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotent
            "fmm_energy"]
 
 
+@contextlib.contextmanager
+def _on(device, stream):
+    """Make ``device`` current and, when given, ``stream`` torch's current
+    stream, so that every temporary and output tensor of a call is
+    allocated on (and recorded against) the stream the library enqueues
+    its kernels on."""
+    with torch.cuda.device(device):
+        if stream is None:
+            yield
+        else:
+            with torch.cuda.stream(stream):
+                yield
+
+
+def _check_out(t, shape, dtype, device, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device == device
+            and t.dtype == dtype and tuple(t.shape) == tuple(shape) and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)} "
+                         f"on {device}")
+
+
 def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = None,
            field: bool = True, stream=None):
     """Direct-sum potential (and field) at ``targets`` (int64 indices into
     pos, CUDA) or at every point; runs in the library's direct kernel."""
     if not (pos.is_cuda and q.is_cuda):
         raise ValueError("pos and q must be CUDA tensors")
-    pos = pos.to(torch.float64).contiguous()
-    q = q.contiguous()
-    prec = FMM_FP64 if q.dtype == torch.float64 else FMM_FP32
+    if pos.dim() != 2 or pos.shape[1] != 3 or q.dim() != 1 or q.shape[0] != pos.shape[0]:
+        raise ValueError("pos must be [N, 3] and q [N]")
+    if q.dtype not in (torch.float64, torch.float32):
+        raise ValueError("q must be float64 or float32")
     n = pos.shape[0]
-    nt = n if targets is None else targets.numel()
-    if targets is not None:
-        targets = targets.to(device=pos.device, dtype=torch.int64).contiguous()
-    pot = torch.empty(nt, dtype=q.dtype, device=q.device)
-    fld = torch.empty((nt, 3), dtype=q.dtype, device=q.device) if field else None
-    with torch.cuda.device(pos.device):
+    with _on(pos.device, stream):
+        pos = pos.to(torch.float64).contiguous()
+        q = q.contiguous()
+        prec = FMM_FP64 if q.dtype == torch.float64 else FMM_FP32
+        nt = n if targets is None else targets.numel()
+        if targets is not None:
+            targets = targets.to(device=pos.device, dtype=torch.int64).contiguous()
+            if nt and (int(targets.min()) < 0 or int(targets.max()) >= n):
+                raise ValueError("targets must index points in [0, N)")
+        pot = torch.empty(nt, dtype=q.dtype, device=q.device)
+        fld = torch.empty((nt, 3), dtype=q.dtype, device=q.device) if field else None
         check(lib().fmm_direct(ctypes.c_void_p(pos.data_ptr()), n, ctypes.c_void_p(q.data_ptr()),
                                prec, ctypes.c_void_p(targets.data_ptr()) if targets is not None else None,
                                nt, ctypes.c_void_p(pot.data_ptr()),
                                ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
-                               _stream_ptr(stream)))
+                               _stream_ptr(None)))
     return pot, fld
 
 
@@ -113,10 +141,11 @@ class Plan:
         return {k: getattr(inf, k) for k, _ in FmmPlanInfo._fields_}
 
     def _vec(self, x: torch.Tensor, name: str):
-        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.dtype):
-            raise ValueError(f"{name} must be a CUDA {self.dtype} tensor")
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.dtype
+                and x.device == self.device):
+            raise ValueError(f"{name} must be a CUDA {self.dtype} tensor on {self.device}")
         xx = x.reshape(1, -1) if x.dim() == 1 else x
-        if xx.shape[1] != self.n:
+        if xx.dim() != 2 or xx.shape[1] != self.n:
             raise ValueError(f"{name} has the wrong number of points")
         return xx.contiguous()
 
@@ -124,15 +153,16 @@ class Plan:
         """The adjoint operator: G-hat^T q (and its field), same shapes as
         evaluate."""
         single = q.dim() == 1
-        qq = self._vec(q, "q")
-        R = qq.shape[0]
-        pot = torch.empty((R, self.n), dtype=self.dtype, device=q.device)
-        fld = torch.empty((R, self.n, 3), dtype=self.dtype, device=q.device) if field else None
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
+            qq = self._vec(q, "q")
+            R = qq.shape[0]
+            pot = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
+            fld = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
+                   if field else None)
             check(lib().fmm_evaluate_transposed(self._h, ctypes.c_void_p(qq.data_ptr()), R,
                                                 ctypes.c_void_p(pot.data_ptr()),
                                                 ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
-                                                _stream_ptr(stream)))
+                                                _stream_ptr(None)))
         if single:
             return pot[0], (fld[0] if fld is not None else None)
         return pot, fld
@@ -143,41 +173,54 @@ class Plan:
         grad_q = G-hat^T g, grad_x = g grad u-hat + q grad(G-hat^T g)
         (grad_x is None when field_fwd is None)."""
         single = g.dim() == 1
-        gg = self._vec(g, "g")
-        R = gg.shape[0]
-        qq = self._vec(q, "q") if field_fwd is not None else None
-        ff = field_fwd.reshape(R, self.n, 3).contiguous() if field_fwd is not None else None
-        gq = torch.empty((R, self.n), dtype=self.dtype, device=g.device)
-        gx = torch.empty((R, self.n, 3), dtype=self.dtype, device=g.device) if ff is not None else None
-        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
+            gg = self._vec(g, "g")
+            R = gg.shape[0]
+            qq = self._vec(q, "q") if field_fwd is not None else None
+            ff = None
+            if field_fwd is not None:
+                if not (isinstance(field_fwd, torch.Tensor) and field_fwd.is_cuda
+                        and field_fwd.dtype == self.dtype and field_fwd.numel() == 3 * R * self.n):
+                    raise ValueError(f"field_fwd must be a CUDA {self.dtype} tensor of "
+                                     f"{R} x {self.n} x 3 values")
+                ff = field_fwd.reshape(R, self.n, 3).contiguous()
+            gq = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
+            gx = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
+                  if ff is not None else None)
+            vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
             check(lib().fmm_adjoint(self._h, vp(qq), vp(gg), R, vp(ff), vp(gq), vp(gx),
-                                    _stream_ptr(stream)))
+                                    _stream_ptr(None)))
         if single:
             return gq[0], (gx[0] if gx is not None else None)
         return gq, gx
 
     def evaluate(self, q: torch.Tensor, field: bool = True, out=None, stream=None):
         """Potentials (and fields = -grad u) for charges ``q`` ([N] or
-        [R, N], CUDA, plan precision).  Returns (pot, field or None)."""
+        [R, N], CUDA, plan precision).  Returns (pot, field or None).
+        ``out`` = (pot [R, N], field [R, N, 3] or None) reuses caller
+        buffers (contiguous, plan dtype, plan device)."""
         if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == self.dtype):
             raise ValueError(f"q must be a CUDA {self.dtype} tensor")
         single = q.dim() == 1
         qq = q.reshape(1, -1) if single else q
-        if qq.shape[1] != self.n:
+        if qq.dim() != 2 or qq.shape[1] != self.n:
             raise ValueError("q has the wrong number of points")
-        qq = qq.contiguous()
         R = qq.shape[0]
-        if out is None:
-            pot = torch.empty((R, self.n), dtype=self.dtype, device=q.device)
-            fld = torch.empty((R, self.n, 3), dtype=self.dtype, device=q.device) if field else None
-        else:
-            pot, fld = out
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
+            qq = qq.contiguous()
+            if out is None:
+                pot = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
+                fld = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
+                       if field else None)
+            else:
+                pot, fld = out
+                _check_out(pot, (R, self.n), self.dtype, self.device, "out[0] (pot)")
+                if fld is not None:
+                    _check_out(fld, (R, self.n, 3), self.dtype, self.device, "out[1] (field)")
             check(lib().fmm_evaluate(self._h, ctypes.c_void_p(qq.data_ptr()), R,
                                      ctypes.c_void_p(pot.data_ptr()),
                                      ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
-                                     _stream_ptr(stream)))
+                                     _stream_ptr(None)))
         if single:
             return pot[0], (fld[0] if fld is not None else None)
         return pot, fld
@@ -186,11 +229,11 @@ class Plan:
         """Time the near-field source groups and the P2M/L2P leaves per wave
         on charges ``q`` ([N], CUDA, plan precision) and keep the fastest
         (fmm_plan_autotune).  Returns the chosen values."""
-        qq = self._vec(q, "q")
         g, lw = ctypes.c_int(), ctypes.c_int()
-        with torch.cuda.device(self.device):
+        with _on(self.device, stream):
+            qq = self._vec(q, "q")
             check(lib().fmm_plan_autotune(self._h, ctypes.c_void_p(qq.data_ptr()),
-                                          _stream_ptr(stream), ctypes.byref(g),
+                                          _stream_ptr(None), ctypes.byref(g),
                                           ctypes.byref(lw)))
         return {"p2p_groups": g.value, "leaves_per_wave": lw.value}
 

@@ -72,37 +72,58 @@ class Lists:
 
 def build_lists(tree: Tree, theta: float, tie: str = "src") -> Lists:
     """Cross-level level-marching lists for sources = targets."""
-    L, nch = tree.L, 1 << tree.s
-    off = tree.level_off
-    avg = level_mean_radius(tree)
+    return build_lists_st(tree, tree, theta, tie)
+
+
+def build_lists_st(stree: Tree, ttree: Tree, theta: float, tie: str = "src") -> Lists:
+    """Cross-level level-marching lists between a source hierarchy and a
+    target hierarchy (Sec. II.B, the generalisation to separate sources and
+    targets): source boxes of level ls are tested against target boxes of
+    level lt, the march choosing which level to refine from the two trees'
+    own level-mean radii; a tree that has reached its leaves stops being
+    refined, so the trees may differ in depth.  M2L pairs are global box ids
+    of their own trees (source id in ``stree``, target id in ``ttree``);
+    P2P pairs are leaf indices of their own trees."""
+    Ls, Lt = stree.L, ttree.L
+    ns, nt = 1 << stree.s, 1 << ttree.s
+    offs, offt = stree.level_off, ttree.level_off
+    avg_s, avg_t = level_mean_radius(stree), level_mean_radius(ttree)
     src = np.zeros(1, dtype=np.int64)  # box index within its level
     tgt = np.zeros(1, dtype=np.int64)
     ls = lt = 0
     steps = [(0, 0)]
     m2l_s, m2l_t = [], []
-    while len(src) and not (ls == L and lt == L):
-        if ls == L:
+    # Reading: the march starts by testing the pair of roots itself (two
+    # separate hierarchies can be well separated as a whole); with sources =
+    # targets the roots coincide (d = 0) and are never admissible.
+    ok = admissible(stree.centre[:1], stree.radius[:1], ttree.centre[:1], ttree.radius[:1], theta)
+    if ok[0]:
+        m2l_s.append(np.zeros(1, np.int64))
+        m2l_t.append(np.zeros(1, np.int64))
+        src = tgt = np.zeros(0, np.int64)
+    while len(src) and not (ls == Ls and lt == Lt):
+        if ls == Ls:
             side = "tgt"
-        elif lt == L:
+        elif lt == Lt:
             side = "src"
-        elif avg[ls] > avg[lt]:
+        elif avg_s[ls] > avg_t[lt]:
             side = "src"
-        elif avg[ls] < avg[lt]:
+        elif avg_s[ls] < avg_t[lt]:
             side = "tgt"
         else:
             side = tie
         if side == "src":
-            src = (src[:, None] * nch + np.arange(nch)[None, :]).ravel()
-            tgt = np.repeat(tgt, nch)
+            src = (src[:, None] * ns + np.arange(ns)[None, :]).ravel()
+            tgt = np.repeat(tgt, ns)
             ls += 1
         else:
-            tgt = (tgt[:, None] * nch + np.arange(nch)[None, :]).ravel()
-            src = np.repeat(src, nch)
+            tgt = (tgt[:, None] * nt + np.arange(nt)[None, :]).ravel()
+            src = np.repeat(src, nt)
             lt += 1
         steps.append((ls, lt))
-        gs, gt = src + off[ls], tgt + off[lt]
-        ok = admissible(tree.centre[gs], tree.radius[gs],
-                        tree.centre[gt], tree.radius[gt], theta)
+        gs, gt = src + offs[ls], tgt + offt[lt]
+        ok = admissible(stree.centre[gs], stree.radius[gs],
+                        ttree.centre[gt], ttree.radius[gt], theta)
         m2l_s.append(gs[ok])
         m2l_t.append(gt[ok])
         src, tgt = src[~ok], tgt[~ok]
@@ -110,8 +131,8 @@ def build_lists(tree: Tree, theta: float, tie: str = "src") -> Lists:
     m2l_t = np.concatenate(m2l_t) if m2l_t else np.zeros(0, np.int64)
     o = np.lexsort((m2l_s, m2l_t))
     m2l_s, m2l_t = m2l_s[o], m2l_t[o]
-    if ls != L or lt != L:
-        # the working set emptied before the leaf level: nothing is direct
+    if ls != Ls or lt != Lt:
+        # the working set emptied before the leaf levels: nothing is direct
         src = tgt = np.zeros(0, np.int64)
     o = np.lexsort((src, tgt))
     return Lists(m2l_src=m2l_s, m2l_tgt=m2l_t, p2p_src=src[o], p2p_tgt=tgt[o],

@@ -70,12 +70,14 @@ class Lists:
     steps: list
 
 
-def build_lists(tree: Tree, theta: float, tie: str = "src") -> Lists:
-    """Cross-level level-marching lists for sources = targets."""
-    return build_lists_st(tree, tree, theta, tie)
+def build_lists(tree: Tree, theta: float, tie: str = "src", mode: str = "cross") -> Lists:
+    """Level-marching lists for sources = targets (``mode`` as in
+    ``build_lists_st``)."""
+    return build_lists_st(tree, tree, theta, tie, mode)
 
 
-def build_lists_st(stree: Tree, ttree: Tree, theta: float, tie: str = "src") -> Lists:
+def build_lists_st(stree: Tree, ttree: Tree, theta: float, tie: str = "src",
+                   mode: str = "cross") -> Lists:
     """Cross-level level-marching lists between a source hierarchy and a
     target hierarchy (Sec. II.B, the generalisation to separate sources and
     targets): source boxes of level ls are tested against target boxes of
@@ -83,7 +85,13 @@ def build_lists_st(stree: Tree, ttree: Tree, theta: float, tie: str = "src") -> 
     own level-mean radii; a tree that has reached its leaves stops being
     refined, so the trees may differ in depth.  M2L pairs are global box ids
     of their own trees (source id in ``stree``, target id in ``ttree``);
-    P2P pairs are leaf indices of their own trees."""
+    P2P pairs are leaf indices of their own trees.
+
+    ``mode="same"`` gives the same-level lists of the enumerated procedure
+    at the start of Sec. II.B (the lists of Engblom's criterion): every step
+    refines both sides, so boxes are only ever compared with boxes of their
+    own level, and the children of well-separated pairs are skipped; once
+    one tree has reached its leaves only the other is refined."""
     Ls, Lt = stree.L, ttree.L
     ns, nt = 1 << stree.s, 1 << ttree.s
     offs, offt = stree.level_off, ttree.level_off
@@ -103,23 +111,26 @@ def build_lists_st(stree: Tree, ttree: Tree, theta: float, tie: str = "src") -> 
         src = tgt = np.zeros(0, np.int64)
     while len(src) and not (ls == Ls and lt == Lt):
         if ls == Ls:
-            side = "tgt"
+            sides = ("tgt",)
         elif lt == Lt:
-            side = "src"
+            sides = ("src",)
+        elif mode == "same":
+            sides = ("src", "tgt")
         elif avg_s[ls] > avg_t[lt]:
-            side = "src"
+            sides = ("src",)
         elif avg_s[ls] < avg_t[lt]:
-            side = "tgt"
+            sides = ("tgt",)
         else:
-            side = tie
-        if side == "src":
-            src = (src[:, None] * ns + np.arange(ns)[None, :]).ravel()
-            tgt = np.repeat(tgt, ns)
-            ls += 1
-        else:
-            tgt = (tgt[:, None] * nt + np.arange(nt)[None, :]).ravel()
-            src = np.repeat(src, nt)
-            lt += 1
+            sides = (tie,)
+        for side in sides:
+            if side == "src":
+                src = (src[:, None] * ns + np.arange(ns)[None, :]).ravel()
+                tgt = np.repeat(tgt, ns)
+                ls += 1
+            else:
+                tgt = (tgt[:, None] * nt + np.arange(nt)[None, :]).ravel()
+                src = np.repeat(src, nt)
+                lt += 1
         steps.append((ls, lt))
         gs, gt = src + offs[ls], tgt + offt[lt]
         ok = admissible(stree.centre[gs], stree.radius[gs],

@@ -160,6 +160,10 @@ def main():
                     help="skip the multi-vector and uneven-problem-set variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter scale)")
+    ap.add_argument("--counters", action="store_true",
+                    help="only the headline pass (plan, autotune, warm-up, timed steps) and, with "
+                         "--copy-calibration, the calibration copy: the program to run under "
+                         "rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the FMM library has no multi-GPU path "
@@ -169,6 +173,9 @@ def main():
     import workloads
 
     pos, q = workloads.uniform_cube(args.n, 0)
+    if args.counters:
+        counters_run(args, pos, q)
+        return
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -299,6 +306,8 @@ def main():
         res_variants.update(run_uneven(F, torch, dev, args, timed, rel))
     if not args.only_headline:
         res_variants.update(run_paper_sets(F, torch, dev, pos_d, q64, timed))
+        res_variants.update(run_clustered(F, torch, dev, args, timed, rel, linf))
+        res_variants.update(run_plummer(F, torch, dev, args, timed, rel, linf))
 
     # roofline of the dominant kernel of the headline pass (one launch per pass)
     dom = max(per_stage, key=per_stage.get)
@@ -471,6 +480,133 @@ def run_uneven(F, torch, dev, args, timed, rel, k=16):
     log(f"uneven {k} problems (N={N}) fp32: graph {ms_g:.3f} ms ({N / ms_g / 1e3:.1f} Mpoints/s), "
         f"eager {ms_e:.3f} ms, separate plans {ms_s:.3f} ms; rel-L2 pot {eu:.2e} field {ef:.2e}")
     return out
+
+
+def counters_run(args, pos, q):
+    """The headline pass alone, for hardware-counter runs: every kernel of
+    one evaluation appears (steps + warmup) times, plus once per autotune
+    candidate; then optionally one plain device copy of 256 MiB whose
+    FETCH_SIZE / WRITE_SIZE calibrate the HBM byte counters."""
+    import torch
+
+    import paper_2511_15269_amd as F
+    dev = torch.device("cuda:0")
+    pos_d = torch.from_numpy(pos).to(dev)
+    dt = torch.float64 if args.precision == "fp64" else torch.float32
+    qd = torch.from_numpy(q).to(dev).to(dt)
+    plan = F.Plan(pos_d, p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
+                  precision=args.precision)
+    tiles = plan.autotune(qd)
+    pot = torch.empty((1, args.n), dtype=dt, device=dev)
+    fld = torch.empty((1, args.n, 3), dtype=dt, device=dev)
+    for _ in range(args.warmup + args.steps):
+        plan.evaluate(qd.reshape(1, -1), out=(pot, fld))
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        a = torch.empty(1 << 25, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    print(json.dumps({"counters_run": True, "passes": args.warmup + args.steps, "tiles": tiles,
+                      "source_sha256": kernel_source_hash()}), flush=True)
+
+
+def dominant_roofline(stages, info, p, n, dtype, fwd_bwd=False):
+    """Algorithmic rate of the slowest stage of a pass (M2L or P2P, whose
+    work the plan's counts give) against the vector peak of ``dtype``."""
+    dom = max(("m2l", "p2p"), key=lambda k: stages[k])
+    if dom == "p2p":
+        flops = 20.0 * info["p2p_interactions"]
+    else:
+        flops = info["n_m2l"] * m2l_flops(p)
+    achieved = flops / (stages[dom] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": dom, "kernel_ms": stages[dom], "achieved": achieved,
+            "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[dtype]}
+
+
+def profiled_stages(plan, fn, passes=5):
+    """Mean per-stage milliseconds of ``passes`` calls of fn (each one pass)."""
+    plan.set_profiling(True)
+    for _ in range(passes):
+        fn()
+    st, n = plan.read_profile()
+    plan.set_profiling(False)
+    return {k: v / max(n, 1) for k, v in st.items()}
+
+
+def run_clustered(F, torch, dev, args, timed, rel, linf, n=1 << 20):
+    """The highly non-uniform set: 8 Gaussians (sigma = 0.01) plus 5% of the
+    points on a sphere shell, charges +-1, p = 10, FP32, potential and field
+    (theta = 0.7, s = 3, leaf <= 128), accuracy over every point against the
+    FP64 direct sum."""
+    import workloads
+    pos, q = workloads.clustered(n, 0)
+    pos_d = torch.from_numpy(pos).to(dev)
+    q64 = torch.from_numpy(q).to(dev)
+    p, th = 10, 0.7
+    plan = F.Plan(pos_d, p=p, leaf_max=args.leaf, splits=args.splits, theta=th,
+                  precision="fp32")
+    qd = q64.float()
+    plan.autotune(qd)
+    pot = torch.empty((1, n), dtype=torch.float32, device=dev)
+    fld = torch.empty((1, n, 3), dtype=torch.float32, device=dev)
+    fn = lambda: plan.evaluate(qd.reshape(1, n), out=(pot, fld))
+    ms = timed(fn, args.steps, args.warmup)
+    stages = profiled_stages(plan, fn)
+    ud, fd = F.direct(pos_d, q64)
+    ud, fd = ud.cpu().numpy(), fd.cpu().numpy()
+    u, f = pot[0].double().cpu().numpy(), fld[0].double().cpu().numpy()
+    info = plan.info()
+    out = {"ms_per_step": ms, "mpoints_s": n / ms / 1e3, "p": p, "theta": th,
+           "splits": args.splits, "leaf_max": args.leaf, "precision": "fp32",
+           "rel_l2_pot": rel(u, ud), "rel_l2_field": rel(f, fd), "rel_linf_pot": linf(u, ud),
+           "rel_linf_field": linf(f, fd), "depth": info["depth"], "stage_ms": stages,
+           "roofline": dominant_roofline(stages, info, p, n, "f32")}
+    log(f"clustered 2^20 p=10 fp32: {ms:.3f} ms ({n / ms / 1e3:.1f} Mpoints/s), rel-L2 pot "
+        f"{out['rel_l2_pot']:.2e} field {out['rel_l2_field']:.2e}, roofline "
+        f"{out['roofline']['kernel']} {out['roofline']['frac']:.3f}")
+    return {"fwd_fp32_clustered1m_p10": out}
+
+
+def run_plummer(F, torch, dev, args, timed, rel, linf, n=1 << 20):
+    """Plummer sphere (a = 0.1), charges in (0, 1], FP32 forward + adjoint of
+    E = 1/2 sum q u (dE/dq, dE/dx), p = 8, theta = 0.5, s = 3, leaf <= 128;
+    accuracy over every point against the direct-sum gradient
+    (dE/dq = u, dE/dx = q grad u)."""
+    import workloads
+    pos, q = workloads.plummer(n, 0)
+    pos_d = torch.from_numpy(pos).to(dev)
+    q64 = torch.from_numpy(q).to(dev)
+    p, th = 8, 0.5
+    plan = F.Plan(pos_d, p=p, leaf_max=args.leaf, splits=args.splits, theta=th,
+                  precision="fp32")
+    qd = q64.float()
+    plan.autotune(qd)
+    half = 0.5 * qd
+    res = {}
+
+    def fn():
+        u, f = plan.evaluate(qd)
+        gq, gx = plan.adjoint(qd, half, f)
+        res["u"], res["gq"], res["gx"] = u, gq, gx
+    ms = timed(fn, args.steps, args.warmup)
+    ms_fwd = timed(lambda: plan.evaluate(qd), args.steps, args.warmup)
+    stages = profiled_stages(plan, lambda: plan.evaluate(qd))
+    ud, fd = F.direct(pos_d, q64)
+    ud, fd = ud.cpu().numpy(), fd.cpu().numpy()
+    dq = (0.5 * res["u"] + res["gq"]).double().cpu().numpy()
+    dx = res["gx"].double().cpu().numpy()
+    want_dx = -q[:, None] * fd
+    info = plan.info()
+    out = {"ms_per_step": ms, "mpoints_s": n / ms / 1e3, "fwd_ms": ms_fwd,
+           "p": p, "theta": th, "splits": args.splits, "leaf_max": args.leaf,
+           "precision": "fp32", "rel_l2_dEdq": rel(dq, ud), "rel_l2_dEdx": rel(dx, want_dx),
+           "rel_linf_dEdq": linf(dq, ud), "rel_linf_dEdx": linf(dx, want_dx),
+           "depth": info["depth"], "stage_ms_fwd": stages,
+           "roofline_fwd": dominant_roofline(stages, info, p, n, "f32")}
+    log(f"plummer 2^20 fwd+bwd fp32: {ms:.3f} ms ({n / ms / 1e3:.1f} Mpoints/s), rel-L2 dE/dq "
+        f"{out['rel_l2_dEdq']:.2e} dE/dx {out['rel_l2_dEdx']:.2e}")
+    return {"fwd_bwd_fp32_plummer1m": out}
 
 
 def m2l_flops(p: int) -> float:

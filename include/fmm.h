@@ -30,13 +30,14 @@
 #ifndef FMM_H_
 #define FMM_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 1
+#define FMM_ABI_VERSION 2
 
 typedef enum {
   FMM_OK = 0,
@@ -53,9 +54,19 @@ typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
 
 typedef enum { FMM_TIE_SOURCE = 0, FMM_TIE_TARGET = 1 } fmm_tie;
 
+/* Interaction lists (Sec. II.B).  Cross-level: the level march that
+ * refines one side per step, so a source box of level l may pair with a
+ * target box of level l or l+1 (the paper's default).  Same-level: the
+ * enumerated procedure at the start of Sec. II.B, boxes compared only with
+ * boxes of their own level (every step refines both sides); for one point
+ * set these lists are symmetric. */
+typedef enum { FMM_LISTS_CROSS_LEVEL = 0, FMM_LISTS_SAME_LEVEL = 1 } fmm_lists;
+
 /* Method parameters (Sec. II.A-II.B; Table II). */
 typedef struct {
-  int p;            /* expansion order, 1 <= p <= FMM_MAX_ORDER            */
+  int p;            /* expansion order p of Sec. II.C (degrees 0..p);
+                       FMM_MIN_ORDER <= p <= FMM_MAX_ORDER are compiled;
+                       p < 0 is FMM_EINVAL, other p FMM_ENOTSUP            */
   int leaf_max;     /* N_max: levels are added until every box holds at
                        most leaf_max points; must be >= 2^splits            */
   int splits;       /* s: binary splits per level, 1..3 (2^s children)   */
@@ -66,8 +77,14 @@ typedef struct {
                        source and target level are equal (Sec. II.B, the
                        enumerated rule 2 says source)                      */
   int max_rhs;      /* largest number of charge vectors per evaluate, >= 1 */
+  int lists;        /* fmm_lists: cross-level (0) or same-level (1)        */
 } fmm_params;
 
+/* Orders with compiled kernels.  Each translation keeps one interaction's
+ * (p+1)^2 coefficients in one lane's registers, fully unrolled per order;
+ * above p = 10 that state no longer fits a lane (the FP64 M2L already
+ * spills a little at p = 10).  p = 0 (monopoles only) is not built.       */
+#define FMM_MIN_ORDER 1
 #define FMM_MAX_ORDER 10
 
 typedef struct fmm_plan fmm_plan;
@@ -82,8 +99,27 @@ typedef struct {
   int64_t n_m2l;        /* multipole-to-local pairs (all levels)           */
   int64_t n_p2p;        /* leaf-leaf direct pairs (including self pairs)   */
   int64_t p2p_interactions; /* sum over direct pairs of |src| * |tgt|     */
-  int64_t device_bytes; /* device memory held by the plan                  */
+  int64_t device_bytes; /* device memory held by the plan (all of it)      */
+  int64_t workspace_bytes; /* of which the evaluation workspace (see
+                              fmm_plan_workspace_bytes)                    */
 } fmm_plan_info;
+
+/* Source of the plan's device memory (fmm_plan_create_ex).  alloc returns
+ * `bytes` of device memory of the current device, aligned to 256 bytes, or
+ * NULL on failure; free releases a block alloc returned.  `stream` is the
+ * stream given to the create call (a hipStream_t): the plan uses the
+ * memory on it, and frees nothing before its work there is done.  Both
+ * callbacks run on the calling thread, inside the create call (the tree and
+ * list build also takes its temporaries from alloc and returns them before
+ * the call ends), inside fmm_plan_autotune (temporary outputs) and inside
+ * fmm_plan_destroy; ctx is passed through.  The per-process operator
+ * tables (a few hundred KB per order and precision, shared by all plans)
+ * are not plan memory and come from hipMalloc.                           */
+typedef struct {
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+  void* ctx;
+} fmm_allocator;
 
 /* Version of this ABI (FMM_ABI_VERSION of the built library). */
 int fmm_abi_version(void);
@@ -105,9 +141,63 @@ const char* fmm_last_error(void);
  * bounding box of a box's points, radius = half its diagonal.  Lists: the
  * cross-level level march of Sec. II.B; a pair at distance 0 is never
  * admissible.  Errors: FMM_EINVAL (parameters, n, NULL, non-finite
- * position), FMM_ENOTSUP (p above FMM_MAX_ORDER), FMM_ENOMEM, FMM_EDEVICE. */
+ * position), FMM_ENOTSUP (p outside FMM_MIN_ORDER..FMM_MAX_ORDER),
+ * FMM_ENOMEM, FMM_EDEVICE. */
 fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
                            void* stream, fmm_plan** out);
+
+/* fmm_plan_create with the plan's device memory taken from `allocator`
+ * (NULL: hipMalloc/hipFree).  flags must be 0.  Errors: as
+ * fmm_plan_create, plus FMM_EINVAL for an allocator without both
+ * callbacks, unknown flags or a block not aligned to 256 bytes, and
+ * FMM_ENOMEM when alloc returns NULL (everything allocated so far is
+ * returned through free). */
+fmm_status fmm_plan_create_ex(const double* pos, int64_t n, const fmm_params* prm,
+                              const fmm_allocator* allocator, unsigned flags, void* stream,
+                              fmm_plan** out);
+
+/* A plan with separate sources and targets (Sec. II.B, the generalisation
+ * to distinct source and target points, used by the paper's inverse-design
+ * example in Sec. III.B): potentials and fields of charges at the ns points
+ * src are evaluated at the nt points tgt.
+ *   src    device, double[ns][3], the charge positions (read only, copied)
+ *   tgt    device, double[nt][3], the evaluation points (read only, copied)
+ * Each point set gets its own tree (Sec. II.A, same parameters; the depths
+ * may differ).  The lists come from the cross-level level march between
+ * the two trees (Sec. II.B): each step refines the side whose level has the
+ * larger mean box radius (the side tie_refine names on equal means), a side
+ * that has reached its leaves is no longer refined, and the march starts
+ * by testing the pair of roots (two point sets far apart interact through
+ * one M2L pair).  A target may coincide with a source: such pairs
+ * contribute nothing.  On this plan fmm_evaluate takes q as [nrhs][ns] and
+ * writes pot [nrhs][nt] and field [nrhs][nt][3]; fmm_evaluate_transposed
+ * takes [nrhs][nt] and writes [nrhs][ns] (the adjoint map, from the
+ * targets back to the sources); fmm_adjoint takes g [nrhs][nt], writes
+ * grad_q [nrhs][ns] and needs grad_x = NULL (FMM_ENOTSUP otherwise).
+ * Every charge vector is evaluated in its own pass (no 32-vector form).
+ * fmm_plan_get_info reports n = ns + nt and the boxes and leaves of both
+ * trees: the source tree's boxes and leaves come first, then the target
+ * tree's; fmm_plan_get_tree's perm gives input indices within each point
+ * set, fmm_plan_get_lists global box and leaf ids.  allocator and flags as
+ * for fmm_plan_create_ex.  Errors: as fmm_plan_create_ex (ns and nt are
+ * each checked as n; ns + nt < 2^31). */
+fmm_status fmm_plan_create_st(const double* src, int64_t ns, const double* tgt, int64_t nt,
+                              const fmm_params* prm, const fmm_allocator* allocator,
+                              unsigned flags, void* stream, fmm_plan** out);
+
+/* Device bytes of the evaluation workspace of a plan of n points with
+ * these parameters (fmm_plan_create): the buffers every evaluation writes
+ * and reads -- leaf-ordered source records (32 n), multipole and local
+ * expansions (2 x nbox x (p+1)^2 values), the near field (4 n values), the
+ * adjoint's field (3 n values) and, for FP32 plans with max_rhs > 1, their
+ * 32-vector copies -- each rounded up to 256 bytes; the plan takes it as one
+ * allocation.  Exact: nbox = sum_{l<=L} 2^{s l} follows from n, leaf_max,
+ * splits and max_depth alone.  The tree and the interaction lists (and the
+ * batched form's M2L partial rows, one row per work item), whose size
+ * depends on where the points are, come on top: fmm_plan_get_info reports
+ * both figures of a built plan.  Host only: needs no device, allocates
+ * nothing.  Errors: FMM_EINVAL (NULL, n or parameters), FMM_ENOTSUP (p). */
+fmm_status fmm_plan_workspace_bytes(int64_t n, const fmm_params* prm, int64_t* bytes);
 
 /* One plan over several independent problems of uneven sizes (beyond the
  * paper, which treats one system per hierarchy; each problem's tree and
@@ -128,6 +218,12 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
  * Errors: as fmm_plan_create, plus FMM_EINVAL for bad offsets. */
 fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int nprob,
                                  const fmm_params* prm, void* stream, fmm_plan** out);
+
+/* fmm_multi_plan_create with device memory from `allocator` (as
+ * fmm_plan_create_ex). */
+fmm_status fmm_multi_plan_create_ex(const double* pos, const int64_t* offsets, int nprob,
+                                    const fmm_params* prm, const fmm_allocator* allocator,
+                                    unsigned flags, void* stream, fmm_plan** out);
 
 /* Sizes of the plan (host struct, written on success). */
 fmm_status fmm_plan_get_info(const fmm_plan* plan, fmm_plan_info* info);

@@ -17,11 +17,11 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
-                   STAGES, FMMError, FmmParams, FmmPlanInfo, check, lib)
+from ._lib import (ALLOC_FN, FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
+                   FREE_FN, STAGES, FmmAllocator, FMMError, FmmParams, FmmPlanInfo, check, lib)
 
 __all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotential",
-           "fmm_energy"]
+           "fmm_energy", "workspace_bytes", "torch_allocator"]
 
 
 @contextlib.contextmanager
@@ -76,12 +76,44 @@ def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = No
 
 
 def params(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16,
-           precision="fp64", tie="source", max_rhs=1) -> FmmParams:
+           precision="fp64", tie="source", max_rhs=1, lists="cross") -> FmmParams:
+    if lists not in ("cross", "same"):
+        raise ValueError("lists must be 'cross' (cross-level) or 'same' (same-level)")
     return FmmParams(p=p, leaf_max=leaf_max, splits=splits, theta=float(theta),
                      max_depth=max_depth,
                      precision=FMM_FP64 if precision == "fp64" else FMM_FP32,
                      tie_refine=FMM_TIE_SOURCE if tie == "source" else FMM_TIE_TARGET,
-                     max_rhs=max_rhs)
+                     max_rhs=max_rhs, lists=1 if lists == "same" else 0)
+
+
+def workspace_bytes(n: int, **kw) -> int:
+    """Device bytes of the evaluation workspace of a plan of ``n`` points
+    (fmm_plan_workspace_bytes; keywords as for ``params``)."""
+    out = ctypes.c_int64()
+    prm = params(**kw)
+    check(lib().fmm_plan_workspace_bytes(int(n), ctypes.byref(prm), ctypes.byref(out)))
+    return out.value
+
+
+def torch_allocator(device) -> FmmAllocator:
+    """An fmm_allocator whose callbacks take device memory from torch's
+    caching allocator (on the stream the library names), so that plan
+    memory is part of torch's pool.  Keep the returned object alive as long
+    as any plan created with it."""
+    dev = torch.device(device).index or 0
+
+    def _alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:
+            return None
+
+    def _free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = FmmAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    a._keep = (_alloc, _free)
+    return a
 
 
 def _stream_ptr(stream):
@@ -95,36 +127,63 @@ class Plan:
 
     With ``sizes`` (problem sizes summing to N), ``pos`` holds several
     independent problems back to back; each gets its own tree and lists and
-    every evaluation covers all of them at once (fmm_multi_plan_create)."""
+    every evaluation covers all of them at once (fmm_multi_plan_create).
+
+    With ``targets`` ([M, 3]), the charges sit at ``pos`` and potentials
+    are evaluated at the M target points, each point set with its own tree
+    (fmm_plan_create_st): evaluate takes q [N] and returns [M] values,
+    evaluate_transposed the reverse."""
 
     def __init__(self, pos: torch.Tensor, p=8, leaf_max=128, splits=2, theta=0.7,
                  max_depth=16, precision="fp64", tie="source", max_rhs=1, stream=None,
-                 sizes=None):
+                 sizes=None, allocator=None, targets=None, lists="cross"):
         if not (isinstance(pos, torch.Tensor) and pos.is_cuda):
             raise ValueError("pos must be a CUDA tensor")
         if pos.dim() != 2 or pos.shape[1] != 3:
             raise ValueError("pos must have shape [N, 3]")
         pos = pos.to(torch.float64).contiguous()
-        self.n = pos.shape[0]
+        self.n = pos.shape[0]          # charges per vector
+        self.n_out = self.n            # evaluation points
+        self.separate = targets is not None
         self.device = pos.device
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.max_rhs = max_rhs
-        self._prm = params(p, leaf_max, splits, theta, max_depth, precision, tie, max_rhs)
+        self._prm = params(p, leaf_max, splits, theta, max_depth, precision, tie, max_rhs, lists)
         self._h = ctypes.c_void_p()
+        # allocator: None (hipMalloc), "torch" (torch's caching allocator) or
+        # an FmmAllocator; kept alive with the plan
+        if allocator == "torch":
+            allocator = torch_allocator(self.device)
+        self._alloc = allocator
+        ap = ctypes.byref(allocator) if allocator is not None else None
         with torch.cuda.device(self.device):
-            if sizes is None:
-                check(lib().fmm_plan_create(ctypes.c_void_p(pos.data_ptr()), self.n,
-                                            ctypes.byref(self._prm), _stream_ptr(stream),
-                                            ctypes.byref(self._h)))
+            if targets is not None:
+                if sizes is not None:
+                    raise ValueError("targets and sizes cannot be combined")
+                if not (isinstance(targets, torch.Tensor) and targets.is_cuda
+                        and targets.device == self.device and targets.dim() == 2
+                        and targets.shape[1] == 3):
+                    raise ValueError("targets must be a CUDA tensor of shape [M, 3] on the "
+                                     "device of pos")
+                tgt = targets.to(torch.float64).contiguous()
+                self.n_out = tgt.shape[0]
+                check(lib().fmm_plan_create_st(ctypes.c_void_p(pos.data_ptr()), self.n,
+                                               ctypes.c_void_p(tgt.data_ptr()), self.n_out,
+                                               ctypes.byref(self._prm), ap, 0,
+                                               _stream_ptr(stream), ctypes.byref(self._h)))
+            elif sizes is None:
+                check(lib().fmm_plan_create_ex(ctypes.c_void_p(pos.data_ptr()), self.n,
+                                               ctypes.byref(self._prm), ap, 0,
+                                               _stream_ptr(stream), ctypes.byref(self._h)))
             else:
                 off = np.concatenate([[0], np.cumsum(np.asarray(sizes, np.int64))])
                 if off[-1] != self.n:
                     raise ValueError("sizes must sum to the number of points")
                 self.offsets = off
-                check(lib().fmm_multi_plan_create(
+                check(lib().fmm_multi_plan_create_ex(
                     ctypes.c_void_p(pos.data_ptr()),
                     off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
-                    ctypes.byref(self._prm), _stream_ptr(stream), ctypes.byref(self._h)))
+                    ctypes.byref(self._prm), ap, 0, _stream_ptr(stream), ctypes.byref(self._h)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -140,12 +199,13 @@ class Plan:
         check(lib().fmm_plan_get_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in FmmPlanInfo._fields_}
 
-    def _vec(self, x: torch.Tensor, name: str):
+    def _vec(self, x: torch.Tensor, name: str, n: int | None = None):
+        n = self.n if n is None else n
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.dtype
                 and x.device == self.device):
             raise ValueError(f"{name} must be a CUDA {self.dtype} tensor on {self.device}")
         xx = x.reshape(1, -1) if x.dim() == 1 else x
-        if xx.dim() != 2 or xx.shape[1] != self.n:
+        if xx.dim() != 2 or xx.shape[1] != n:
             raise ValueError(f"{name} has the wrong number of points")
         return xx.contiguous()
 
@@ -154,7 +214,7 @@ class Plan:
         evaluate."""
         single = q.dim() == 1
         with _on(self.device, stream):
-            qq = self._vec(q, "q")
+            qq = self._vec(q, "q", self.n_out)
             R = qq.shape[0]
             pot = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
             fld = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
@@ -174,16 +234,17 @@ class Plan:
         (grad_x is None when field_fwd is None)."""
         single = g.dim() == 1
         with _on(self.device, stream):
-            gg = self._vec(g, "g")
+            gg = self._vec(g, "g", self.n_out)
             R = gg.shape[0]
             qq = self._vec(q, "q") if field_fwd is not None else None
             ff = None
             if field_fwd is not None:
+                m = self.n_out
                 if not (isinstance(field_fwd, torch.Tensor) and field_fwd.is_cuda
-                        and field_fwd.dtype == self.dtype and field_fwd.numel() == 3 * R * self.n):
+                        and field_fwd.dtype == self.dtype and field_fwd.numel() == 3 * R * m):
                     raise ValueError(f"field_fwd must be a CUDA {self.dtype} tensor of "
-                                     f"{R} x {self.n} x 3 values")
-                ff = field_fwd.reshape(R, self.n, 3).contiguous()
+                                     f"{R} x {m} x 3 values")
+                ff = field_fwd.reshape(R, m, 3).contiguous()
             gq = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
             gx = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
                   if ff is not None else None)
@@ -206,17 +267,18 @@ class Plan:
         if qq.dim() != 2 or qq.shape[1] != self.n:
             raise ValueError("q has the wrong number of points")
         R = qq.shape[0]
+        m = self.n_out
         with _on(self.device, stream):
             qq = qq.contiguous()
             if out is None:
-                pot = torch.empty((R, self.n), dtype=self.dtype, device=self.device)
-                fld = (torch.empty((R, self.n, 3), dtype=self.dtype, device=self.device)
+                pot = torch.empty((R, m), dtype=self.dtype, device=self.device)
+                fld = (torch.empty((R, m, 3), dtype=self.dtype, device=self.device)
                        if field else None)
             else:
                 pot, fld = out
-                _check_out(pot, (R, self.n), self.dtype, self.device, "out[0] (pot)")
+                _check_out(pot, (R, m), self.dtype, self.device, "out[0] (pot)")
                 if fld is not None:
-                    _check_out(fld, (R, self.n, 3), self.dtype, self.device, "out[1] (field)")
+                    _check_out(fld, (R, m, 3), self.dtype, self.device, "out[1] (field)")
             check(lib().fmm_evaluate(self._h, ctypes.c_void_p(qq.data_ptr()), R,
                                      ctypes.c_void_p(pot.data_ptr()),
                                      ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
@@ -284,12 +346,13 @@ class Graph:
     def __init__(self, plan: Plan, q: torch.Tensor, field: bool = True,
                  transposed: bool = False):
         self.plan = plan
-        self.q = plan._vec(q, "q")
+        nin, nout = (plan.n_out, plan.n) if transposed else (plan.n, plan.n_out)
+        self.q = plan._vec(q, "q", nin)
         if self.q.data_ptr() != q.data_ptr():
             raise ValueError("q must be contiguous (the graph keeps its address)")
         R = self.q.shape[0]
-        self.pot = torch.empty((R, plan.n), dtype=plan.dtype, device=q.device)
-        self.field = (torch.empty((R, plan.n, 3), dtype=plan.dtype, device=q.device)
+        self.pot = torch.empty((R, nout), dtype=plan.dtype, device=q.device)
+        self.field = (torch.empty((R, nout, 3), dtype=plan.dtype, device=q.device)
                       if field else None)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(plan.device):
@@ -316,11 +379,14 @@ class Graph:
 class FMMPotential(torch.autograd.Function):
     """u-hat = FMM(q, x) on a fixed plan, differentiable in q and in the
     point positions x (hierarchy frozen: tree, lists and box centres do not
-    move).  ``pos`` must hold the positions the plan was built from."""
+    move).  ``pos`` must hold the positions the plan was built from.  On a
+    plan with separate targets only q is differentiable (pass pos=None)."""
 
     @staticmethod
     def forward(ctx, q, pos, plan):
-        need_x = pos.requires_grad
+        need_x = pos is not None and pos.requires_grad
+        if need_x and plan.separate:
+            raise ValueError("position gradients need a plan over one point set")
         u, f = plan.evaluate(q, field=need_x)
         ctx.plan = plan
         ctx.save_for_backward(q, f if need_x else None)

@@ -11,7 +11,9 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ENOTSUP, FMM_ESTATE = range(6)
 STATUS_NAMES = {0: "FMM_OK", 1: "FMM_EINVAL", 2: "FMM_ENOMEM", 3: "FMM_EDEVICE",
                 4: "FMM_ENOTSUP", 5: "FMM_ESTATE"}
 FMM_FP64, FMM_FP32 = 0, 1
+FMM_MIN_ORDER, FMM_MAX_ORDER = 1, 10
 FMM_TIE_SOURCE, FMM_TIE_TARGET = 0, 1
+FMM_LISTS_CROSS_LEVEL, FMM_LISTS_SAME_LEVEL = 0, 1
 FMM_NSTAGES = 7
 STAGES = ("sort", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p")
 
@@ -20,7 +22,8 @@ class FmmParams(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("leaf_max", ctypes.c_int),
                 ("splits", ctypes.c_int), ("theta", ctypes.c_double),
                 ("max_depth", ctypes.c_int), ("precision", ctypes.c_int),
-                ("tie_refine", ctypes.c_int), ("max_rhs", ctypes.c_int)]
+                ("tie_refine", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("lists", ctypes.c_int)]
 
 
 class FmmPlanInfo(ctypes.Structure):
@@ -28,7 +31,15 @@ class FmmPlanInfo(ctypes.Structure):
                 ("splits", ctypes.c_int32), ("nbox", ctypes.c_int64),
                 ("nleaf", ctypes.c_int64), ("n_m2l", ctypes.c_int64),
                 ("n_p2p", ctypes.c_int64), ("p2p_interactions", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class FmmAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class FMMError(RuntimeError):
@@ -52,6 +63,16 @@ def lib() -> ctypes.CDLL:
         L.fmm_abi_version.restype = ctypes.c_int
         L.fmm_last_error.restype = ctypes.c_char_p
         L.fmm_plan_create.argtypes = [vp, i64, ctypes.POINTER(FmmParams), vp, ctypes.POINTER(vp)]
+        L.fmm_plan_create_ex.argtypes = [vp, i64, ctypes.POINTER(FmmParams),
+                                         ctypes.POINTER(FmmAllocator), ctypes.c_uint, vp,
+                                         ctypes.POINTER(vp)]
+        L.fmm_multi_plan_create_ex.argtypes = [vp, i64p, ctypes.c_int, ctypes.POINTER(FmmParams),
+                                               ctypes.POINTER(FmmAllocator), ctypes.c_uint, vp,
+                                               ctypes.POINTER(vp)]
+        L.fmm_plan_workspace_bytes.argtypes = [i64, ctypes.POINTER(FmmParams), i64p]
+        L.fmm_plan_create_st.argtypes = [vp, i64, vp, i64, ctypes.POINTER(FmmParams),
+                                         ctypes.POINTER(FmmAllocator), ctypes.c_uint, vp,
+                                         ctypes.POINTER(vp)]
         L.fmm_plan_get_info.argtypes = [vp, ctypes.POINTER(FmmPlanInfo)]
         L.fmm_evaluate.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
         L.fmm_plan_get_tree.argtypes = [vp, i64p, i64p, dp, dp]
@@ -75,7 +96,8 @@ def lib() -> ctypes.CDLL:
                   "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile",
                   "fmm_evaluate_transposed", "fmm_adjoint", "fmm_multi_plan_create",
                   "fmm_graph_create", "fmm_graph_launch", "fmm_graph_destroy",
-                  "fmm_plan_autotune"):
+                  "fmm_plan_autotune", "fmm_plan_create_ex", "fmm_multi_plan_create_ex",
+                  "fmm_plan_workspace_bytes", "fmm_plan_create_st"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -18,17 +18,74 @@ void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 const char* last_error() { return g_err.c_str(); }
 
-void* plan_alloc(fmm_plan* pl, size_t bytes) {
-  void* p = nullptr;
+void* dev_alloc(fmm_plan* pl, size_t bytes) {
   bytes = bytes ? bytes : 16;
+  void* p = nullptr;
+  if (pl->allocator.alloc) {
+    p = pl->allocator.alloc(pl->allocator.ctx, bytes, (void*)pl->alloc_stream);
+    if (!p)
+      throw Error{FMM_ENOMEM,
+                  "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+    if ((uintptr_t)p % 256 != 0) {
+      pl->allocator.free(pl->allocator.ctx, p, (void*)pl->alloc_stream);
+      throw Error{FMM_EINVAL, "allocator callback returned memory not aligned to 256 bytes"};
+    }
+    return p;
+  }
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error{FMM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
   }
+  return p;
+}
+
+void dev_free(fmm_plan* pl, void* p) {
+  if (!p) return;
+  if (pl->allocator.free)
+    pl->allocator.free(pl->allocator.ctx, p, (void*)pl->alloc_stream);
+  else
+    (void)hipFree(p);
+}
+
+void* plan_alloc(fmm_plan* pl, size_t bytes) {
+  void* p = dev_alloc(pl, bytes);
+  bytes = bytes ? bytes : 16;
   pl->bufs.push_back(DevBuf{p, bytes});
   pl->device_bytes += bytes;
   return p;
+}
+
+WorkspaceLayout workspace_layout(int64_t n, int64_t nbox, const fmm_params& prm, bool batched) {
+  const size_t es = prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+  const size_t K = (size_t)ncoef(prm.p);
+  const size_t W = (size_t)batch_width() * sizeof(float);
+  WorkspaceLayout L;
+  const size_t sz[10] = {32 * (size_t)n,
+                         es * K * (size_t)nbox,
+                         es * K * (size_t)nbox,
+                         es * 4 * (size_t)n,
+                         es * 3 * (size_t)n,
+                         batched ? W * n : 0,
+                         batched ? W * K * nbox : 0,
+                         batched ? W * K * nbox : 0,
+                         batched ? W * n : 0,
+                         batched ? W * 3 * n : 0};
+  size_t o = 0;
+  for (int i = 0; i < 10; ++i) {
+    L.off[i] = o;
+    L.size[i] = sz[i];
+    o += (sz[i] + 255) / 256 * 256;
+    if (i == 3) L.forward = o;
+  }
+  L.total = o;
+  return L;
+}
+
+void bind_workspace(Workspace& ws, char* base, const WorkspaceLayout& L, int count) {
+  void** slot[10] = {&ws.src, &ws.C, &ws.D, &ws.near, &ws.field_t,
+                     &ws.bq,  &ws.bC, &ws.bD, &ws.bpot, &ws.bfld};
+  for (int i = 0; i < 10; ++i) *slot[i] = (i < count && L.size[i] > 0) ? base + L.off[i] : nullptr;
 }
 
 hipEvent_t take_event(fmm_plan* pl) {
@@ -49,15 +106,14 @@ void release_profile(fmm_plan* pl) {
 }
 
 void plan_free_all(fmm_plan* pl) {
-  for (auto& b : pl->bufs) (void)hipFree(b.ptr);
+  for (auto& b : pl->bufs) dev_free(pl, b.ptr);
   pl->bufs.clear();
   pl->device_bytes = 0;
 }
 
-void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st) {
+void make_steps(fmm_plan* pl, const std::vector<std::vector<TreeDesc>>& groups,
+                hipStream_t st) {
   const int s = pl->s;
-  int Lmax = 0;
-  for (const TreeDesc& t : trees) Lmax = std::max(Lmax, t.L);
   auto upload = [&](const std::vector<int32_t>& v) {
     int32_t* d = (int32_t*)plan_alloc(pl, sizeof(int32_t) * v.size());
     if (!v.empty())
@@ -66,13 +122,12 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
     return d;
   };
   std::vector<int32_t> lb;
-  for (const TreeDesc& t : trees) {
-    const int64_t nl = t.level_off[t.L + 1] - t.level_off[t.L];
-    for (int64_t i = 0; i < nl; ++i) lb.push_back((int32_t)(t.box_base + t.level_off[t.L] + i));
-  }
+  for (const auto& trees : groups)
+    for (const TreeDesc& t : trees) {
+      const int64_t nl = t.level_off[t.L + 1] - t.level_off[t.L];
+      for (int64_t i = 0; i < nl; ++i) lb.push_back((int32_t)(t.box_base + t.level_off[t.L] + i));
+    }
   pl->leaf_box = upload(lb);
-  pl->m2m_steps.clear();
-  pl->l2l_steps.clear();
   // Boxes whose expansions matter: those in an M2L pair (either role, so
   // both the forward and the transposed pass are covered) and all their
   // descendants.  Multipoles of other boxes are never read; locals of other
@@ -91,64 +146,88 @@ void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st
     for (int64_t b = 0; b < pl->nbox; ++b)
       if (ptr[b + 1] > ptr[b]) active[b] = 1;
     for (int64_t k = 0; k < F.n_m2l; ++k) active[src[k]] = 1;
-    for (const TreeDesc& t : trees)
-      for (int l = 1; l <= t.L; ++l)
-        for (int64_t i = 0; i < t.level_off[l + 1] - t.level_off[l]; ++i) {
-          const int64_t b = t.box_base + t.level_off[l] + i;
-          if (active[t.box_base + t.level_off[l - 1] + (i >> s)]) active[b] = 1;
+    for (const auto& trees : groups)
+      for (const TreeDesc& t : trees)
+        for (int l = 1; l <= t.L; ++l)
+          for (int64_t i = 0; i < t.level_off[l + 1] - t.level_off[l]; ++i) {
+            const int64_t b = t.box_base + t.level_off[l] + i;
+            if (active[t.box_base + t.level_off[l - 1] + (i >> s)]) active[b] = 1;
+          }
+  }
+  std::vector<std::vector<int32_t>> all_of(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const std::vector<TreeDesc>& trees = groups[g];
+    Side& S = pl->side[g];
+    S.m2m_steps.clear();
+    S.l2l_steps.clear();
+    int Lmax = 0;
+    for (const TreeDesc& t : trees) Lmax = std::max(Lmax, t.L);
+    // Upward: step h takes the parents h+1 levels above each tree's leaves.
+    for (int h = 0; h < Lmax; ++h) {
+      std::vector<int32_t> a, b;
+      for (const TreeDesc& t : trees) {
+        const int l = t.L - 1 - h;
+        if (l < 0) continue;
+        const int64_t np = t.level_off[l + 1] - t.level_off[l];
+        for (int64_t i = 0; i < np; ++i) {
+          const int64_t p = t.box_base + t.level_off[l] + i;
+          if (!active[p]) continue;
+          a.push_back((int32_t)p);
+          b.push_back((int32_t)(t.box_base + t.level_off[l + 1] + (i << s)));
         }
-  }
-  // Upward: step h takes the parents h+1 levels above each tree's leaves.
-  for (int h = 0; h < Lmax; ++h) {
-    std::vector<int32_t> a, b;
-    for (const TreeDesc& t : trees) {
-      const int l = t.L - 1 - h;
-      if (l < 0) continue;
-      const int64_t np = t.level_off[l + 1] - t.level_off[l];
-      for (int64_t i = 0; i < np; ++i) {
-        const int64_t p = t.box_base + t.level_off[l] + i;
-        if (!active[p]) continue;
-        a.push_back((int32_t)p);
-        b.push_back((int32_t)(t.box_base + t.level_off[l + 1] + (i << s)));
       }
+      if (a.empty()) continue;
+      Step St;
+      St.n = (int64_t)a.size();
+      St.a = upload(a);
+      St.b = upload(b);
+      S.m2m_steps.push_back(St);
     }
-    if (a.empty()) continue;
-    Step S;
-    S.n = (int64_t)a.size();
-    S.a = upload(a);
-    S.b = upload(b);
-    pl->m2m_steps.push_back(S);
-  }
-  // Downward: every box whose local is formed starts from the sum of its
-  // M2L partials (one launch over all of them); step l then adds the
-  // translated parent local to the boxes of level l of every tree that deep
-  // whose parent has one.
-  std::vector<int32_t> all;
-  for (int l = 0; l <= Lmax; ++l) {
-    std::vector<int32_t> a, b;
-    for (const TreeDesc& t : trees) {
-      if (l > t.L) continue;
-      const int64_t nb = t.level_off[l + 1] - t.level_off[l];
-      for (int64_t i = 0; i < nb; ++i) {
-        const int64_t bx = t.box_base + t.level_off[l] + i;
-        if (!active[bx] && l < t.L) continue;  // leaves are always written
-        all.push_back((int32_t)bx);
-        const int64_t pa = l > 0 ? t.box_base + t.level_off[l - 1] + (i >> s) : -1;
-        if (pa < 0 || !active[pa]) continue;
-        a.push_back((int32_t)bx);
-        b.push_back((int32_t)pa);
+    // Downward: every box whose local is formed starts from the sum of its
+    // M2L translations (written by the M2L kernel, or zero); step l then
+    // adds the translated parent local to the boxes of level l of every tree
+    // that deep whose parent has one.
+    std::vector<int32_t>& all = all_of[g];
+    for (int l = 0; l <= Lmax; ++l) {
+      std::vector<int32_t> a, b;
+      for (const TreeDesc& t : trees) {
+        if (l > t.L) continue;
+        const int64_t nb = t.level_off[l + 1] - t.level_off[l];
+        for (int64_t i = 0; i < nb; ++i) {
+          const int64_t bx = t.box_base + t.level_off[l] + i;
+          if (!active[bx] && l < t.L) continue;  // leaves are always written
+          all.push_back((int32_t)bx);
+          const int64_t pa = l > 0 ? t.box_base + t.level_off[l - 1] + (i >> s) : -1;
+          if (pa < 0 || !active[pa]) continue;
+          a.push_back((int32_t)bx);
+          b.push_back((int32_t)pa);
+        }
       }
+      if (a.empty()) continue;
+      Step St;
+      St.n = (int64_t)a.size();
+      St.a = upload(a);
+      St.b = upload(b);
+      S.l2l_steps.push_back(St);
     }
-    if (a.empty()) continue;
-    Step S;
-    S.n = (int64_t)a.size();
-    S.a = upload(a);
-    S.b = upload(b);
-    pl->l2l_steps.push_back(S);
+    S.l2l_sum.n = (int64_t)all.size();
+    S.l2l_sum.a = upload(all);
+    S.l2l_sum.b = nullptr;
   }
-  pl->l2l_sum.n = (int64_t)all.size();
-  pl->l2l_sum.a = upload(all);
-  pl->l2l_sum.b = nullptr;
+  // boxes whose local is formed but which receive no M2L pair in a direction:
+  // their M2L sum is zero and is written by a fill before the level chain
+  for (int d = 0; d < 2; ++d) {
+    ListSet& L = pl->lists[d];
+    const std::vector<int32_t>& all = all_of[pl->nsides == 1 ? 0 : 1 - d];
+    std::vector<int32_t> ptr(pl->nbox + 1), z;
+    FMM_HIP(hipMemcpyAsync(ptr.data(), L.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
+                           hipMemcpyDeviceToHost, st));
+    FMM_HIP(hipStreamSynchronize(st));
+    for (int32_t b : all)
+      if (ptr[b + 1] == ptr[b]) z.push_back(b);
+    L.n_zero = (int64_t)z.size();
+    L.zero_box = upload(z);
+  }
 }
 
 namespace {
@@ -167,7 +246,7 @@ void check_params(const fmm_params* prm, int64_t n) {
   if (!prm) throw Error{FMM_EINVAL, "params is NULL"};
   if (n < 1 || n >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "n must be in [1, 2^31)"};
   if (prm->splits < 1 || prm->splits > 3) throw Error{FMM_EINVAL, "splits must be 1..3"};
-  if (prm->p < 1) throw Error{FMM_EINVAL, "p must be >= 1"};
+  if (prm->p < 0) throw Error{FMM_EINVAL, "p must be >= 0"};
   if (prm->leaf_max < (1 << prm->splits))
     throw Error{FMM_EINVAL, "leaf_max must be >= 2^splits"};
   if (!(prm->theta > 0.0 && prm->theta < 1.0)) throw Error{FMM_EINVAL, "theta must be in (0,1)"};
@@ -177,7 +256,21 @@ void check_params(const fmm_params* prm, int64_t n) {
   if (prm->tie_refine != FMM_TIE_SOURCE && prm->tie_refine != FMM_TIE_TARGET)
     throw Error{FMM_EINVAL, "tie_refine must be FMM_TIE_SOURCE or FMM_TIE_TARGET"};
   if (prm->max_rhs < 1) throw Error{FMM_EINVAL, "max_rhs must be >= 1"};
-  if (prm->p > FMM_MAX_ORDER) throw Error{FMM_ENOTSUP, "p above FMM_MAX_ORDER"};
+  if (prm->lists != FMM_LISTS_CROSS_LEVEL && prm->lists != FMM_LISTS_SAME_LEVEL)
+    throw Error{FMM_EINVAL, "lists must be FMM_LISTS_CROSS_LEVEL or FMM_LISTS_SAME_LEVEL"};
+  if (prm->p < FMM_MIN_ORDER || prm->p > FMM_MAX_ORDER)
+    throw Error{FMM_ENOTSUP, "p outside FMM_MIN_ORDER..FMM_MAX_ORDER (no compiled kernels)"};
+}
+
+void check_allocator(const fmm_allocator* a, unsigned flags) {
+  if (a && (!a->alloc || !a->free))
+    throw Error{FMM_EINVAL, "allocator needs both an alloc and a free callback"};
+  if (flags != 0u) throw Error{FMM_EINVAL, "unknown plan flags"};
+}
+
+void use_allocator(fmm_plan* pl, const fmm_allocator* a, hipStream_t st) {
+  if (a) pl->allocator = *a;
+  pl->alloc_stream = st;
 }
 
 template <typename F>
@@ -201,6 +294,10 @@ fmm_status guard(F&& f) {
   }
 }
 
+void check_workspace(const fmm_plan* pl) {
+  if (!pl->ws.C) throw Error{FMM_ESTATE, "the plan holds no evaluation workspace"};
+}
+
 void check_device(const fmm_plan* pl) {
   int dev = -1;
   FMM_HIP(hipGetDevice(&dev));
@@ -213,7 +310,7 @@ void check_device(const fmm_plan* pl) {
 // per vector.
 void run_vectors(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
                  hipStream_t st) {
-  if (nrhs > 1 && pl->bq) {
+  if (nrhs > 1 && pl->ws.bq) {
     const int W = batch_width();
     const int64_t n = pl->n;
     for (int r0 = 0; r0 < nrhs; r0 += W) {
@@ -222,14 +319,14 @@ void run_vectors(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void
                      field ? (float*)field + 3 * (int64_t)r0 * n : nullptr, st);
     }
   } else {
-    evaluate(pl, dir, q, nrhs, pot, field, st);
+    evaluate(pl, pl->ws, dir, q, nrhs, pot, field, st);
   }
 }
 
-// Tree, geometry and lists of one point set (plan creation minus the
-// evaluation workspace).
+// Tree and geometry (and, with lists, the interaction lists) of one point
+// set: plan creation minus the level steps and the evaluation workspace.
 void build_structure(fmm_plan* pl, const double* pos, int64_t n, const fmm_params* prm,
-                     hipStream_t st) {
+                     hipStream_t st, bool lists = true) {
   FMM_HIP(hipGetDevice(&pl->device));
   pl->prm = *prm;
   pl->n = n;
@@ -253,31 +350,31 @@ void build_structure(fmm_plan* pl, const double* pos, int64_t n, const fmm_param
   pl->radius = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
   pl->scale = (double*)plan_alloc(pl, sizeof(double) * pl->nbox);
   build_tree(pl, pos, st);
-  build_lists(pl, st);
+  pl->side[0].npt = n;
+  pl->side[0].nleaf = pl->nleaf;
+  if (lists) {
+    const TreeDesc t{pl->L, pl->level_off, 0, 0};
+    build_lists(pl, t, t, st);
+  }
 }
 
-// Evaluation workspace sized from the plan's counts.
+bool batched_plan(const fmm_plan* pl) {
+  return pl->prm.precision == FMM_FP32 && pl->prm.max_rhs > 1 && pl->nsides == 1;
+}
+
+// Evaluation workspace (one allocation, workspace_layout) and the batched
+// M2L partial rows, sized from the plan's counts.
 void alloc_workspace(fmm_plan* pl, hipStream_t st) {
   const fmm_params* prm = &pl->prm;
-  const int64_t n = pl->n;
-  const size_t es = prm->precision == FMM_FP32 ? sizeof(float) : sizeof(double);
-  const size_t K = (size_t)ncoef(prm->p);
-  const size_t ni =
-      (size_t)std::max<int64_t>(std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
-  pl->src = plan_alloc(pl, 32 * (size_t)n);
-  pl->C = plan_alloc(pl, es * K * (size_t)pl->nbox);
-  pl->D = plan_alloc(pl, es * K * (size_t)pl->nbox);
-  pl->partial = plan_alloc(pl, es * K * ni);
-  pl->field_t = plan_alloc(pl, es * 3 * (size_t)n);
-  pl->near = plan_alloc(pl, es * 4 * (size_t)n);
-  if (prm->precision == FMM_FP32 && prm->max_rhs > 1) {
-    const size_t W = (size_t)batch_width() * sizeof(float);
-    pl->bq = plan_alloc(pl, W * n);
-    pl->bC = plan_alloc(pl, W * K * pl->nbox);
-    pl->bD = plan_alloc(pl, W * K * pl->nbox);
-    pl->bpart = plan_alloc(pl, W * K * ni);
-    pl->bpot = plan_alloc(pl, W * n);
-    pl->bfld = plan_alloc(pl, W * 3 * n);
+  const bool bat = batched_plan(pl);
+  const WorkspaceLayout L = workspace_layout(pl->n, pl->nbox, *prm, bat);
+  pl->workspace_bytes = L.total;
+  bind_workspace(pl->ws, (char*)plan_alloc(pl, L.total), L, 10);
+  if (bat) {
+    const size_t K = (size_t)ncoef(prm->p);
+    const size_t ni =
+        (size_t)std::max<int64_t>(std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
+    pl->bpart = plan_alloc(pl, (size_t)batch_width() * sizeof(float) * K * ni);
   }
   pl->tables = get_tables(prm->p, prm->precision, pl->device);
   FMM_HIP(hipStreamSynchronize(st));
@@ -294,17 +391,20 @@ int fmm_abi_version(void) { return FMM_ABI_VERSION; }
 
 const char* fmm_last_error(void) { return fmm::last_error(); }
 
-fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
-                           void* stream, fmm_plan** out) {
+fmm_status fmm_plan_create_ex(const double* pos, int64_t n, const fmm_params* prm,
+                              const fmm_allocator* allocator, unsigned flags, void* stream,
+                              fmm_plan** out) {
   return guard([&] {
     if (!out) throw Error{FMM_EINVAL, "out is NULL"};
     if (!pos) throw Error{FMM_EINVAL, "pos is NULL"};
     check_params(prm, n);
+    check_allocator(allocator, flags);
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
+    use_allocator(pl.get(), allocator, st);
     try {
       build_structure(pl.get(), pos, n, prm, st);
-      make_steps(pl.get(), {TreeDesc{pl->L, pl->level_off, 0}}, st);
+      make_steps(pl.get(), {{TreeDesc{pl->L, pl->level_off, 0, 0}}}, st);
       alloc_workspace(pl.get(), st);
     } catch (...) {
       (void)hipStreamSynchronize(st);
@@ -315,8 +415,14 @@ fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
   });
 }
 
-fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int nprob,
-                                 const fmm_params* prm, void* stream, fmm_plan** out) {
+fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
+                           void* stream, fmm_plan** out) {
+  return fmm_plan_create_ex(pos, n, prm, nullptr, 0u, stream, out);
+}
+
+fmm_status fmm_multi_plan_create_ex(const double* pos, const int64_t* offsets, int nprob,
+                                    const fmm_params* prm, const fmm_allocator* allocator,
+                                    unsigned flags, void* stream, fmm_plan** out) {
   return guard([&] {
     if (!out) throw Error{FMM_EINVAL, "out is NULL"};
     if (!pos || !offsets) throw Error{FMM_EINVAL, "pos and offsets must not be NULL"};
@@ -326,9 +432,11 @@ fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int 
       if (offsets[k + 1] <= offsets[k])
         throw Error{FMM_EINVAL, "every problem needs at least one point"};
     check_params(prm, offsets[nprob]);
+    check_allocator(allocator, flags);
     hipStream_t st = (hipStream_t)stream;
     std::vector<std::unique_ptr<fmm_plan>> subs;
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
+    use_allocator(pl.get(), allocator, st);
     auto free_subs = [&] {
       for (auto& u : subs) plan_free_all(u.get());
       subs.clear();
@@ -336,6 +444,7 @@ fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int 
     try {
       for (int k = 0; k < nprob; ++k) {
         subs.emplace_back(new fmm_plan());
+        use_allocator(subs.back().get(), allocator, st);
         build_structure(subs.back().get(), pos + 3 * offsets[k], offsets[k + 1] - offsets[k], prm,
                         st);
       }
@@ -343,12 +452,16 @@ fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int 
       for (auto& u : subs) sp.push_back(u.get());
       build_union(pl.get(), sp, st);
       std::vector<TreeDesc> trees;
-      int64_t base = 0;
+      int64_t base = 0, lbase = 0;
       for (const fmm_plan* u : sp) {
-        trees.push_back(TreeDesc{u->L, u->level_off, base});
+        trees.push_back(TreeDesc{u->L, u->level_off, base, lbase});
         base += u->nbox;
+        lbase += u->nleaf;
       }
-      make_steps(pl.get(), trees, st);
+      pl->side[0].npt = pl->n;
+      pl->side[0].nleaf = pl->nleaf;
+      make_steps(pl.get(), {trees}, st);
+      (void)hipStreamSynchronize(st);
       free_subs();
       alloc_workspace(pl.get(), st);
     } catch (...) {
@@ -358,6 +471,75 @@ fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int 
       throw;
     }
     *out = pl.release();
+  });
+}
+
+fmm_status fmm_multi_plan_create(const double* pos, const int64_t* offsets, int nprob,
+                                 const fmm_params* prm, void* stream, fmm_plan** out) {
+  return fmm_multi_plan_create_ex(pos, offsets, nprob, prm, nullptr, 0u, stream, out);
+}
+
+fmm_status fmm_plan_create_st(const double* src, int64_t ns, const double* tgt, int64_t nt,
+                              const fmm_params* prm, const fmm_allocator* allocator,
+                              unsigned flags, void* stream, fmm_plan** out) {
+  return guard([&] {
+    if (!out) throw Error{FMM_EINVAL, "out is NULL"};
+    if (!src || !tgt) throw Error{FMM_EINVAL, "src and tgt must not be NULL"};
+    check_params(prm, ns);
+    check_params(prm, nt);
+    if (ns + nt >= ((int64_t)1 << 31)) throw Error{FMM_EINVAL, "ns + nt must be below 2^31"};
+    check_allocator(allocator, flags);
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<fmm_plan> sub[2];
+    std::unique_ptr<fmm_plan> pl(new fmm_plan());
+    use_allocator(pl.get(), allocator, st);
+    auto free_subs = [&] {
+      for (auto& u : sub)
+        if (u) plan_free_all(u.get());
+    };
+    try {
+      const double* pos[2] = {src, tgt};
+      const int64_t cnt[2] = {ns, nt};
+      for (int k = 0; k < 2; ++k) {
+        sub[k].reset(new fmm_plan());
+        use_allocator(sub[k].get(), allocator, st);
+        build_structure(sub[k].get(), pos[k], cnt[k], prm, st, false);
+      }
+      build_union(pl.get(), {sub[0].get(), sub[1].get()}, st, false);
+      pl->nsides = 2;
+      pl->has_dup = true;  // a target may coincide with a source anywhere
+      const TreeDesc ts{sub[0]->L, sub[0]->level_off, 0, 0};
+      const TreeDesc tt{sub[1]->L, sub[1]->level_off, sub[0]->nbox, sub[0]->nleaf};
+      for (int k = 0; k < 2; ++k) {
+        pl->side[k].pt0 = k == 0 ? 0 : ns;
+        pl->side[k].npt = cnt[k];
+        pl->side[k].leaf0 = k == 0 ? 0 : sub[0]->nleaf;
+        pl->side[k].nleaf = sub[k]->nleaf;
+      }
+      build_lists(pl.get(), ts, tt, st);
+      make_steps(pl.get(), {{ts}, {tt}}, st);
+      (void)hipStreamSynchronize(st);
+      free_subs();
+      alloc_workspace(pl.get(), st);
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      free_subs();
+      plan_free_all(pl.get());
+      throw;
+    }
+    *out = pl.release();
+  });
+}
+
+fmm_status fmm_plan_workspace_bytes(int64_t n, const fmm_params* prm, int64_t* bytes) {
+  return guard([&] {
+    if (!bytes) throw Error{FMM_EINVAL, "bytes is NULL"};
+    check_params(prm, n);
+    const int L = depth_for(n, prm->leaf_max, prm->splits, prm->max_depth);
+    int64_t nbox = 0;
+    for (int l = 0; l <= L; ++l) nbox += (int64_t)1 << (prm->splits * l);
+    const bool bat = prm->precision == FMM_FP32 && prm->max_rhs > 1;
+    *bytes = (int64_t)workspace_layout(n, nbox, *prm, bat).total;
   });
 }
 
@@ -374,6 +556,7 @@ fmm_status fmm_plan_get_info(const fmm_plan* pl, fmm_plan_info* info) {
     r.n_p2p = pl->lists[0].n_p2p;
     r.p2p_interactions = pl->p2p_inter;
     r.device_bytes = (int64_t)pl->device_bytes;
+    r.workspace_bytes = (int64_t)pl->workspace_bytes;
     *info = r;
   });
 }
@@ -408,16 +591,21 @@ fmm_status fmm_adjoint(fmm_plan* pl, const void* q, const void* g, int nrhs,
     if (grad_x && (!q || !field_fwd))
       throw Error{FMM_EINVAL, "grad_x needs q and field_fwd"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
+    if (grad_x && pl->nsides == 2)
+      throw Error{FMM_ENOTSUP, "position gradients of a plan with separate targets"};
     check_device(pl);
+    check_workspace(pl);
     const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
     const hipStream_t st = (hipStream_t)stream;
+    // g lives on the target side, grad_q on the source side
+    const size_t ng = (size_t)tgt_side(pl, 0).npt, nq = (size_t)src_side(pl, 0).npt;
     for (int r = 0; r < nrhs; ++r) {
-      const size_t o1 = es * (size_t)pl->n * r, o3 = 3 * o1;
-      fmm::evaluate(pl, 1, (const char*)g + o1, 1, (char*)grad_q + o1,
-                    grad_x ? pl->field_t : nullptr, st);
+      const size_t o1 = es * nq * r, o3 = 3 * o1, og = es * ng * r;
+      fmm::evaluate(pl, pl->ws, 1, (const char*)g + og, 1, (char*)grad_q + o1,
+                    grad_x ? pl->ws.field_t : nullptr, st);
       if (grad_x)
         fmm::adjoint_combine(pl, (const char*)q + o1, (const char*)g + o1,
-                             (const char*)field_fwd + o3, pl->field_t, (char*)grad_x + o3, st);
+                             (const char*)field_fwd + o3, pl->ws.field_t, (char*)grad_x + o3, st);
     }
   });
 }
@@ -604,15 +792,16 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     const bool prof = pl->profiling;
     const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave;
     auto cleanup = [&] {
-      if (pot) (void)hipFree(pot);
-      if (fld) (void)hipFree(fld);
+      if (pot || fld) (void)hipStreamSynchronize(st);
+      dev_free(pl, pot);
+      dev_free(pl, fld);
       if (e0) (void)hipEventDestroy(e0);
       if (e1) (void)hipEventDestroy(e1);
       pl->profiling = prof;
     };
     try {
-      FMM_HIP(hipMalloc(&pot, es * (size_t)pl->n));
-      FMM_HIP(hipMalloc(&fld, es * 3 * (size_t)pl->n));
+      pot = dev_alloc(pl, es * (size_t)pl->n);
+      fld = dev_alloc(pl, es * 3 * (size_t)pl->n);
       FMM_HIP(hipEventCreate(&e0));
       FMM_HIP(hipEventCreate(&e1));
       pl->profiling = false;
@@ -624,9 +813,9 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
           if (!valid_leaves_per_wave(pl, l)) continue;
           pl->p2p_groups = g;
           pl->leaves_per_wave = l;
-          fmm::evaluate(pl, 0, q, 1, pot, fld, st);
+          fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
           FMM_HIP(hipEventRecord(e0, st));
-          for (int r = 0; r < 3; ++r) fmm::evaluate(pl, 0, q, 1, pot, fld, st);
+          for (int r = 0; r < 3; ++r) fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
           FMM_HIP(hipEventRecord(e1, st));
           FMM_HIP(hipEventSynchronize(e1));
           float ms = 0.f;

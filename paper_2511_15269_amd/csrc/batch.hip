@@ -178,6 +178,7 @@ __global__ __launch_bounds__(64) void k_bm2l(
   const int r = threadIdx.x % kRB;
   if (i >= nitems) return;
   const int t = item_tgt[i];
+  if (t < 0) return;  // idle lane of the packed item layout
   const int jb = item_begin[i], je = item_end[i];
   const double tx = cx[t], ty = cy[t], tz = cz[t], rt = scale[t];
   float acc[K];
@@ -431,12 +432,12 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                float* field, hipStream_t st) {
   const int s = pl->s;
   const float* tab = (const float*)pl->tables;
-  float* qL = (float*)pl->bq;
-  float* C = (float*)pl->bC;
-  float* D = (float*)pl->bD;
+  float* qL = (float*)pl->ws.bq;
+  float* C = (float*)pl->ws.bC;
+  float* D = (float*)pl->ws.bD;
   float* part = (float*)pl->bpart;
-  float* potL = (float*)pl->bpot;
-  float* fldL = (float*)pl->bfld;
+  float* potL = (float*)pl->ws.bpot;
+  float* fldL = (float*)pl->ws.bfld;
   const int64_t n = pl->n;
   StageMarks mk(pl);
   // the sort stage is folded into P2M; its timing slot stays empty
@@ -448,7 +449,7 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                                                 tab, C);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
-  for (const Step& S : pl->m2m_steps)
+  for (const Step& S : pl->side[0].m2m_steps)
     k_bm2m<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
                                              pl->scale, tab, C);
   mk.end(kStM2M, st);
@@ -459,10 +460,11 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                                                     pl->cz, pl->scale, C, tab, part);
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
-  if (pl->l2l_sum.n > 0)
-    k_psum<float><<<(unsigned)pl->l2l_sum.n, 256, 0, st>>>(
-        pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr, part, K_<P>::value * kRB, D);
-  for (const Step& S : pl->l2l_steps)
+  const Step& all = pl->side[0].l2l_sum;
+  if (all.n > 0)
+    k_psum<float><<<(unsigned)all.n, 256, 0, st>>>(all.n, all.a, Ls.item_first, Ls.item_cnt,
+                                                   part, K_<P>::value * kRB, D);
+  for (const Step& S : pl->side[0].l2l_steps)
     k_bl2l<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz, pl->scale,
                                              tab, D);
   mk.end(kStL2L, st);

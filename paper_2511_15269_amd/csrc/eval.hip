@@ -20,13 +20,14 @@
 // one interaction (all of its coefficients sit in registers); the operator
 // tables are wave-uniform and are read through the scalar cache.
 //
-//   M2L item: thread = (target box, up to 16 of its sources); partial sums
-//             are added per target in a fixed order by the L2L kernel, so
-//             results do not depend on scheduling (no atomics).
+//   M2L item: thread = (target box, up to a dozen of its sources); the
+//             items of one target share a block and their sums are added
+//             in lane order, so results do not depend on scheduling (the
+//             only atomics are adds to lane-private LDS slots).
 //   M2M:      thread = child box; the 2^s children of a parent sit in
 //             adjacent lanes and are summed with cross-lane shuffles.
-//   L2L:      thread = box of the level; adds its M2L partials and the
-//             shifted local expansion of its parent.
+//   L2L:      thread = box of the level; adds the shifted local expansion
+//             of its parent to the box's M2L sum.
 //   P2M:      block = leaf, thread = point, LDS reduction over points.
 //   L2P:      block = target leaf, thread = target point; writes outputs.
 //   P2P:      block = target leaf, thread = target point; adds the near
@@ -44,7 +45,6 @@ namespace fmm {
 namespace {
 
 using namespace ops;
-constexpr int kM2LThreads = 64;
 
 // ---------------------------------------------------------------- P2M
 // C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole).
@@ -137,34 +137,69 @@ __global__ __launch_bounds__(64) void k_m2m(
 }
 
 // ---------------------------------------------------------------- M2L
+// Lane-private LDS rows, row stride kRow elements: row r of lane l at
+// r * kRow + l.  The stride of 65 puts the rows of one lane in different
+// banks, so that the segment sums below (lanes reading different rows of
+// the same lane) do not collide, while a wave's access to one row stays
+// contiguous.
+constexpr int kRow = 65;
+
+// For every target segment of this block (seg_tgt[g], lanes
+// [seg_lanes[g] & 255, seg_lanes[g] >> 8), g in [sb, se)), adds rows
+// [0, NR) of buf over the segment's lanes in lane order and stores the sums
+// as coefficients k0 .. k0 + NR - 1 of the target's local.
+template <int NR, typename T>
+__device__ __forceinline__ void segment_sums(const T* buf, int k0, int K, int sb, int se,
+                                             const int32_t* __restrict__ seg_tgt,
+                                             const int32_t* __restrict__ seg_lanes, T* D) {
+  const int n = (se - sb) * NR;
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int g = sb + idx / NR, r = idx % NR;
+    const int info = seg_lanes[g];
+    T acc = T(0);
+    for (int l = info & 255; l < (info >> 8); ++l) acc += buf[r * kRow + l];
+    D[(int64_t)seg_tgt[g] * K + k0 + r] = acc;
+  }
+}
+
+// One block = kM2LBlock lanes; lane = one work item (a run of at most a
+// dozen source boxes of one target).  Every lane translates its sources and
+// sums them; the items of one target share the block and their sums are
+// added in lane order into the target's local, D_t = sum of its M2L
+// translations, written once (no partial rows in memory).
 template <int P, typename T>
-__global__ __launch_bounds__(kM2LThreads) void k_m2l(
-    int64_t nitems, const int32_t* __restrict__ item_tgt,
+__global__ __launch_bounds__(kM2LBlock) void k_m2l(
+    int64_t nblocks, const int32_t* __restrict__ item_tgt,
     const int32_t* __restrict__ item_begin, const int32_t* __restrict__ item_end,
-    const int32_t* __restrict__ src, const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
-    const double* __restrict__ scale, const T* __restrict__ C,
-    const T* __restrict__ tab, T* __restrict__ partial) {
+    const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ seg_tgt,
+    const int32_t* __restrict__ seg_lanes, const int32_t* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ C, const T* __restrict__ tab, T* __restrict__ D) {
   constexpr int K = K_<P>::value;
-  const int64_t i =
-      (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const int t = item_tgt[i];
-  const int jb = item_begin[i], je = item_end[i];
-  const double tx = cx[t], ty = cy[t], tz = cz[t], rt = scale[t];
-  // Accumulators: in FP64 with (p+1)^2 > 80 the first 80 coefficients live
-  // in LDS (lane-private slots, coefficient-major so that a wave's 64 slots
-  // are consecutive; 40 KiB per 64-lane block, four blocks fill a CU's
-  // 160 KiB, the occupancy the registers allow anyway) and are updated with
-  // LDS atomic adds that need no registers; the rest stay in registers.
-  constexpr int KL = (sizeof(T) == 8 && K > 80) ? 80 : 0;
-  __shared__ T accl[KL > 0 ? KL : 1][64];
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
-  T acc[K - KL];
+  const int64_t i = b * kM2LBlock + lane;
+  const int t = item_tgt[i];
+  const int jb = item_begin[i], je = item_end[i];  // empty for idle lanes
+  const int tt = t < 0 ? 0 : t;
+  const double tx = cx[tt], ty = cy[tt], tz = cz[tt], rt = scale[tt];
+  // Accumulators: in FP64 with (p+1)^2 > KL the first KL coefficients live
+  // in lane-private LDS rows (78 rows of 65 doubles fit 40 KiB, so four
+  // 64-lane blocks fill a CU's 160 KiB, the occupancy the registers allow
+  // anyway) and are updated with LDS atomic adds that need no registers; the
+  // rest stay in registers.  The rows are then reused to add the items of
+  // each target.
+  constexpr int KL = (sizeof(T) == 8 && K > 78) ? 78 : 0;
+  constexpr int KR = K - KL;                      // accumulators in registers
+  constexpr int CH = KL > 0 ? (KR < KL ? KR : KL) : (KR < 16 ? KR : 16);  // rows per pass
+  constexpr int NROW = KL > 0 ? KL : CH;
+  __shared__ T accl[(NROW - 1) * kRow + kM2LBlock];
+  T acc[KR];
 #pragma unroll
-  for (int k = 0; k < KL; ++k) accl[k][lane] = T(0);
+  for (int k = 0; k < KL; ++k) accl[k * kRow + lane] = T(0);
 #pragma unroll
-  for (int k = 0; k < K - KL; ++k) acc[k] = T(0);
+  for (int k = 0; k < KR; ++k) acc[k] = T(0);
   for (int j = jb; j < je; ++j) {
     const int sidx = src[j];
     T v[K];
@@ -174,19 +209,46 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(
                              tab);
 #pragma unroll
     for (int k = 0; k < KL; ++k)
-      __hip_atomic_fetch_add(&accl[k][lane], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&accl[k * kRow + lane], v[k], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
     for (int k = KL; k < K; ++k) acc[k - KL] += v[k];
   }
+  const int sb = seg_ptr[b], se = seg_ptr[b + 1];
+  __syncthreads();
+  if (KL > 0) {
+    segment_sums<(KL > 0 ? KL : 1), T>(accl, 0, K, sb, se, seg_tgt, seg_lanes, D);
+    __syncthreads();
+  }
+  // register accumulators, CH rows at a time
 #pragma unroll
-  for (int k = 0; k < KL; ++k) partial[i * K + k] = accl[k][lane];
+  for (int c0 = 0; c0 < KR; c0 += CH) {
 #pragma unroll
-  for (int k = KL; k < K; ++k) partial[i * K + k] = acc[k - KL];
+    for (int r = 0; r < CH; ++r)
+      if (c0 + r < KR) accl[r * kRow + lane] = acc[c0 + r];
+    __syncthreads();
+    if (c0 + CH <= KR)
+      segment_sums<CH, T>(accl, KL + c0, K, sb, se, seg_tgt, seg_lanes, D);
+    else
+      segment_sums<(KR % CH > 0 ? KR % CH : 1), T>(accl, KL + c0, K, sb, se, seg_tgt,
+                                                   seg_lanes, D);
+    __syncthreads();
+  }
+}
+
+// D[t] = 0 for the boxes t of the list (locals formed without M2L pairs).
+template <typename T>
+__global__ void k_zero_rows(int64_t nb, const int32_t* __restrict__ boxes, int K,
+                            T* __restrict__ D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * K) return;
+  const int64_t i = e / K;
+  D[(int64_t)boxes[i] * K + (e - i * K)] = T(0);
 }
 
 // ---------------------------------------------------------------- L2L
 // D_t += L2L(D_parent) for the boxes of one level (D_t holds the sum of
-// t's M2L partials, k_psum).
+// t's M2L translations).
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_l2l(
     int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
@@ -280,7 +342,9 @@ constexpr int kChunk = 8;
 // P2P: writes -1/(4 pi) sum q/r and the matching field over the direct list,
 // in leaf order (near[i] and near[n + 3 i + c]); L2P adds the far field and
 // writes the outputs in input order.
-// Block = target leaf, lane = target point.  G source groups: lanes
+// Block = target leaf leaf0 + blockIdx.x, lane = target point (position from
+// the plan's leaf-ordered coordinates; the sources' records are this
+// pass's, written by P2M).  G source groups: lanes
 // [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
 // G-th source point starting at point g.  G = 1 keeps all source reads
 // wave-uniform (scalar loads).  G = 2, 4 fill the wave when leaves hold at
@@ -292,14 +356,15 @@ constexpr int kChunk = 8;
 // combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
-    int64_t n, const int32_t* __restrict__ leaf_start, const Src<T>* __restrict__ src,
-    const int32_t* __restrict__ p2p_ptr, const int32_t* __restrict__ p2p_src, int dup,
-    T* __restrict__ near) {
+    int64_t n, int64_t leaf0, const int32_t* __restrict__ leaf_start,
+    const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ zs,
+    const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
+    const int32_t* __restrict__ p2p_src, int dup, T* __restrict__ near) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   // G > 1: one source leaf (at most TL points) staged as 16-byte words
   __shared__ __align__(32) double2 stage[G > 1 ? 2 * TL : 1];
-  const int leaf = blockIdx.x;
+  const int leaf = (int)(leaf0 + blockIdx.x);
   const int lane = threadIdx.x;
   const int g = G == 1 ? 0 : lane / TL;
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
@@ -307,7 +372,8 @@ __global__ __launch_bounds__(64) void k_p2p(
   for (int i0 = st; i0 < en; i0 += TL) {
     const int i = i0 + lane % TL;
     const bool live = i < en;
-    const Src<T> a = src[live ? i : st];
+    const int ia = live ? i : st;
+    const Src<T> a{xs[ia], ys[ia], zs[ia], T(0)};
     T u = T(0), gx = T(0), gy = T(0), gz = T(0);
     T cu = T(0), cgx = T(0), cgy = T(0), cgz = T(0);
     for (int k = pb; k < pe; ++k) {
@@ -411,15 +477,18 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // stream does not pay: it fills the GPU and delays the small level-by-level
 // launches of the far field by as much as it hides.)
 template <int P, typename T>
-void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStream_t st) {
+void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* field,
+         hipStream_t st) {
   const int s = pl->s;
   const T* tab = (const T*)pl->tables;
-  Src<T>* src = (Src<T>*)pl->src;
-  T* C = (T*)pl->C;
-  T* D = (T*)pl->D;
-  T* part = (T*)pl->partial;
-  T* near = (T*)pl->near;
+  Src<T>* src = (Src<T>*)ws.src;
+  T* C = (T*)ws.C;
+  T* D = (T*)ws.D;
+  T* near = (T*)ws.near;
   const int64_t n = pl->n;
+  const ListSet& Ls = pl->lists[dir];
+  const Side& SS = src_side(pl, dir);  // charges: P2M, M2M
+  const Side& TS = tgt_side(pl, dir);  // evaluation points: L2L, P2P, L2P
   StageMarks mk(pl);
   // the sort stage (charges into leaf-ordered source records) is folded
   // into P2M; its timing slot stays empty
@@ -428,12 +497,12 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   // far field
   // leaves per wave for P2M and L2P: every lane holds at most one point
   const int GL = leaves_per_wave(pl);
-  const int64_t nl = pl->nleaf;
-  const unsigned nb_l = (unsigned)((nl + GL - 1) / GL);
+  const int64_t nls = SS.nleaf, nlt = TS.nleaf;
   mk.begin(kStP2M, st);
   auto p2m = [&](auto kern) {
-    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs,
-                              pl->perm, q, src, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+    kern<<<(unsigned)((nls + GL - 1) / GL), 64, 0, st>>>(
+        nls, pl->leaf_box + SS.leaf0, pl->leaf_start + SS.leaf0, pl->xs, pl->ys, pl->zs,
+        pl->perm, q, src, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
   };
   if (GL == 1) p2m(k_p2m<P, T, 1>);
   else if (GL == 2) p2m(k_p2m<P, T, 2>);
@@ -441,23 +510,23 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   else p2m(k_p2m<P, T, 8>);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
-  for (const Step& S : pl->m2m_steps) {
+  for (const Step& S : SS.m2m_steps) {
     const int64_t nchild = S.n << s;
     k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
                                                    pl->scale, tab, C);
   }
   mk.end(kStM2M, st);
   mk.begin(kStM2L, st);
-  if (Ls.n_items > 0)
-    k_m2l<P, T><<<blocks(Ls.n_items, kM2LThreads), kM2LThreads, 0, st>>>(
-        Ls.n_items, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.m2l_src, pl->cx, pl->cy,
-        pl->cz, pl->scale, C, tab, part);
+  if (Ls.n_blocks > 0)
+    k_m2l<P, T><<<(unsigned)Ls.n_blocks, kM2LBlock, 0, st>>>(
+        Ls.n_blocks, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.seg_ptr, Ls.seg_tgt,
+        Ls.seg_lanes, Ls.m2l_src, pl->cx, pl->cy, pl->cz, pl->scale, C, tab, D);
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
-  if (pl->l2l_sum.n > 0)
-    k_psum<T><<<(unsigned)pl->l2l_sum.n, K_<P>::value <= 64 ? 64 : 128, 0, st>>>(
-        pl->l2l_sum.n, pl->l2l_sum.a, Ls.item_ptr, part, K_<P>::value, D);
-  for (const Step& S : pl->l2l_steps)
+  if (Ls.n_zero > 0)
+    k_zero_rows<T><<<blocks(Ls.n_zero * K_<P>::value, 256), 256, 0, st>>>(
+        Ls.n_zero, Ls.zero_box, K_<P>::value, D);
+  for (const Step& S : TS.l2l_steps)
     k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz,
                                                 pl->scale, tab, D);
   mk.end(kStL2L, st);
@@ -465,8 +534,8 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.begin(kStP2P, st);
   const int G = p2p_groups(pl);
   auto p2p = [&](auto kern) {
-    kern<<<(unsigned)pl->nleaf, 64, 0, st>>>(n, pl->leaf_start, src, Ls.p2p_ptr, Ls.p2p_src,
-                                              pl->has_dup ? 1 : 0, near);
+    kern<<<(unsigned)nlt, 64, 0, st>>>(n, TS.leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs, src,
+                                       Ls.p2p_ptr, Ls.p2p_src, pl->has_dup ? 1 : 0, near);
   };
   if (field) {
     if (G == 1) p2p(k_p2p<T, true, 1>);
@@ -480,9 +549,9 @@ void run(fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field, hipStrea
   mk.end(kStP2P, st);
   mk.begin(kStL2P, st);
   auto l2p = [&](auto kern) {
-    kern<<<nb_l, 64, 0, st>>>(nl, pl->leaf_box, pl->leaf_start, pl->perm, pl->xs, pl->ys,
-                              pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, n, near, pot,
-                              field);
+    kern<<<(unsigned)((nlt + GL - 1) / GL), 64, 0, st>>>(
+        nlt, pl->leaf_box + TS.leaf0, pl->leaf_start + TS.leaf0, pl->perm, pl->xs, pl->ys,
+        pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, n, near, pot, field);
   };
   if (field) {
     if (GL == 1) l2p(k_l2p<P, T, true, 1>);
@@ -522,12 +591,12 @@ int leaves_per_wave(const fmm_plan* pl) {
 namespace {
 
 template <typename T>
-void dispatch(int p, fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* field,
-              hipStream_t st) {
+void dispatch(int p, fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot,
+              T* field, hipStream_t st) {
   switch (p) {
 #define FMM_CASE(PP) \
   case PP:           \
-    run<PP, T>(pl, Ls, q, pot, field, st); \
+    run<PP, T>(pl, ws, dir, q, pot, field, st); \
     break;
     FMM_CASE(1) FMM_CASE(2) FMM_CASE(3) FMM_CASE(4) FMM_CASE(5)
     FMM_CASE(6) FMM_CASE(7) FMM_CASE(8) FMM_CASE(9) FMM_CASE(10)
@@ -539,17 +608,17 @@ void dispatch(int p, fmm_plan* pl, const ListSet& Ls, const T* q, T* pot, T* fie
 
 }  // namespace
 
-void evaluate(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
-              hipStream_t st) {
-  const int64_t n = pl->n;
-  const ListSet& Ls = pl->lists[dir];
+void evaluate(fmm_plan* pl, const Workspace& ws, int dir, const void* q, int nrhs, void* pot,
+              void* field, hipStream_t st) {
+  // vector r of q has the source side's points, of pot/field the target side's
+  const int64_t nq = src_side(pl, dir).npt, nu = tgt_side(pl, dir).npt;
   for (int r = 0; r < nrhs; ++r) {
     if (pl->prm.precision == FMM_FP32) {
-      dispatch<float>(pl->prm.p, pl, Ls, (const float*)q + r * n, (float*)pot + r * n,
-                      field ? (float*)field + 3 * r * n : nullptr, st);
+      dispatch<float>(pl->prm.p, pl, ws, dir, (const float*)q + r * nq, (float*)pot + r * nu,
+                      field ? (float*)field + 3 * r * nu : nullptr, st);
     } else {
-      dispatch<double>(pl->prm.p, pl, Ls, (const double*)q + r * n, (double*)pot + r * n,
-                       field ? (double*)field + 3 * r * n : nullptr, st);
+      dispatch<double>(pl->prm.p, pl, ws, dir, (const double*)q + r * nq, (double*)pot + r * nu,
+                       field ? (double*)field + 3 * r * nu : nullptr, st);
     }
   }
 }

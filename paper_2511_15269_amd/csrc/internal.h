@@ -45,21 +45,64 @@ struct Tables {
   void* dev32 = nullptr;     // device copy (float)
 };
 
-// Interaction lists of one direction, CSR by target.  M2L work items: item
-// i covers pairs [item_begin[i], item_end[i]) of target item_tgt[i]; the
-// items of one target are consecutive and item_ptr[t]..item_ptr[t+1] lists
-// them.
+// Lanes of one M2L block (one wave).
+constexpr int kM2LBlock = 64;
+
+// Interaction lists of one direction, CSR by target.  M2L work items: lane
+// i covers pairs [item_begin[i], item_end[i]) of target item_tgt[i] (-1 for
+// an idle lane); the items are packed into blocks of kM2LBlock lanes, the
+// items of one target consecutive inside one block (item_first[t],
+// item_cnt[t]).  Block b holds the target segments seg_ptr[b] ..
+// seg_ptr[b+1]-1: segment g covers lanes [seg_lanes[g] & 255,
+// seg_lanes[g] >> 8) of target seg_tgt[g].  zero_box lists the boxes whose
+// local is formed but which have no pair in this direction (their M2L sum
+// is zero).
 struct ListSet {
   int32_t* m2l_ptr = nullptr;  // [nbox+1]
   int32_t* m2l_src = nullptr;  // [n_m2l]
   int32_t* p2p_ptr = nullptr;  // [nleaf+1]
   int32_t* p2p_src = nullptr;  // [n_p2p]
-  int32_t* item_tgt = nullptr;
-  int32_t* item_begin = nullptr;
-  int32_t* item_end = nullptr;
-  int32_t* item_ptr = nullptr;  // [nbox+1]
-  int64_t n_m2l = 0, n_p2p = 0, n_items = 0;
+  int32_t* item_tgt = nullptr;    // [n_items]
+  int32_t* item_begin = nullptr;  // [n_items]
+  int32_t* item_end = nullptr;    // [n_items]
+  int32_t* item_first = nullptr;  // [nbox]
+  int32_t* item_cnt = nullptr;    // [nbox]
+  int32_t* seg_ptr = nullptr;     // [n_blocks+1]
+  int32_t* seg_tgt = nullptr;
+  int32_t* seg_lanes = nullptr;
+  int32_t* zero_box = nullptr;
+  int64_t n_m2l = 0, n_p2p = 0, n_items = 0, n_blocks = 0, n_zero = 0;
 };
+
+// Per-evaluation device buffers (all but the M2L partial rows of the
+// batched form): leaf-ordered source records, expansions, the near field,
+// the adjoint's field and the 32-vector copies.
+struct Workspace {
+  void* src = nullptr;      // [n] {x, y, z, q} in leaf order
+  void* C = nullptr;        // [nbox][K]   multipoles (normalised)
+  void* D = nullptr;        // [nbox][K]   locals (normalised)
+  void* near = nullptr;     // [4n] near field in leaf order: pot [n], field [n][3]
+  void* field_t = nullptr;  // [n][3] field of the transposed pass (adjoint)
+  // multi-vector workspace (FP32 plans with max_rhs > 1), vectors innermost
+  void* bq = nullptr;    // [n][32]
+  void* bC = nullptr;    // [nbox][K][32]
+  void* bD = nullptr;    // [nbox][K][32]
+  void* bpot = nullptr;  // [n][32]
+  void* bfld = nullptr;  // [n][3][32]
+};
+
+// Byte offsets of the workspace buffers inside one allocation, each
+// aligned to 256 bytes, in the order of Workspace; `forward` is the size of
+// the leading part one single-vector evaluation uses (src, C, D, near).
+struct WorkspaceLayout {
+  size_t off[10] = {0};
+  size_t size[10] = {0};
+  size_t forward = 0;
+  size_t total = 0;
+};
+WorkspaceLayout workspace_layout(int64_t n, int64_t nbox, const fmm_params& prm, bool batched);
+// Point the buffers of ws at base + offsets (the first `count` buffers).
+void bind_workspace(Workspace& ws, char* base, const WorkspaceLayout& L, int count);
 
 // One level step of the upward (M2M) or downward (L2L) pass: n boxes a[i]
 // with b[i] = first child (M2M; the 2^s children are consecutive) or parent
@@ -68,6 +111,20 @@ struct Step {
   int32_t* a = nullptr;
   int32_t* b = nullptr;
   int64_t n = 0;
+};
+
+// One side of a plan: the charges (sources) or the evaluation points
+// (targets).  A plan over one point set has one side that plays both
+// roles; a plan with separate sources and targets (Sec. II.B) has the
+// sources as side 0 and the targets as side 1, each with its own tree.
+// Slots [pt0, pt0 + npt) and leaves [leaf0, leaf0 + nleaf) of the plan's
+// concatenated arrays are the side's; its boxes are those of its trees.
+struct Side {
+  int64_t pt0 = 0, npt = 0;
+  int64_t leaf0 = 0, nleaf = 0;
+  std::vector<Step> m2m_steps;  // bottom-up, parents of one level per step
+  std::vector<Step> l2l_steps;  // top-down, boxes of one level with a parent local
+  Step l2l_sum;                 // every box whose local is formed (b unused)
 };
 
 }  // namespace fmm
@@ -98,34 +155,31 @@ struct fmm_plan {
   int p2p_groups = 0;
   int leaves_per_wave = 0;
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
-  std::vector<fmm::Step> m2m_steps;  // bottom-up, parents of one level per step
-  std::vector<fmm::Step> l2l_steps;  // top-down, boxes of one level with a parent local
-  fmm::Step l2l_sum;                 // every box whose local is formed (b unused)
-  int n_problems = 1;                // > 1: union of independent trees
+  int nsides = 1;               // 2: separate sources (side 0) and targets (side 1)
+  fmm::Side side[2];
+  int n_problems = 1;           // > 1: union of independent trees
 
   // lists (device): [0] forward, [1] transposed (every pair reversed; the
   // adjoint operator)
   fmm::ListSet lists[2];
   int64_t p2p_inter = 0;
 
-  // evaluation workspace
-  void* src = nullptr;       // [n] {x, y, z, q} in leaf order
-  void* C = nullptr;         // [nbox][K]   multipoles (normalised)
-  void* D = nullptr;         // [nbox][K]   locals (normalised)
-  void* partial = nullptr;   // [max n_items][K] M2L partial sums
-  void* field_t = nullptr;   // [n][3] field of the transposed pass (adjoint)
-  void* near = nullptr;      // [4n] near field in leaf order: pot [n], field [n][3]
-  // multi-vector workspace (FP32 plans with max_rhs > 1), vectors innermost
-  void* bq = nullptr;     // [n][32]
-  void* bC = nullptr;     // [nbox][K][32]
-  void* bD = nullptr;     // [nbox][K][32]
-  void* bpart = nullptr;  // [max n_items][K][32]
-  void* bpot = nullptr;   // [n][32]
-  void* bfld = nullptr;   // [n][3][32]
+  // evaluation workspace: one device allocation of workspace_bytes carved
+  // into the buffers below (workspace_layout); empty for plans created with
+  // FMM_PLAN_NO_WORKSPACE
+  fmm::Workspace ws;
+  size_t workspace_bytes = 0;
+  // batched M2L partial rows [n_items][K][32] (FP32 plans with max_rhs > 1);
+  // sized by the lists, so held with them
+  void* bpart = nullptr;
   const void* tables = nullptr;  // device operator tables for (p, precision)
 
   std::vector<fmm::DevBuf> bufs;
   size_t device_bytes = 0;
+  // device memory source of the plan (fmm_plan_create_ex), also used for
+  // temporaries during the build; stream passed to the callbacks
+  fmm_allocator allocator{nullptr, nullptr, nullptr};
+  hipStream_t alloc_stream = nullptr;
 
   // stage timing (fmm_plan_set_profiling)
   bool profiling = false;
@@ -142,34 +196,74 @@ struct fmm_graph {
 
 namespace fmm {
 
+// Device memory for the plan (kept until fmm_plan_destroy), through the
+// plan's allocator.
 void* plan_alloc(fmm_plan* pl, size_t bytes);
 void plan_free_all(fmm_plan* pl);
+// Temporary device memory during the build, through the plan's allocator.
+void* dev_alloc(fmm_plan* pl, size_t bytes);
+void dev_free(fmm_plan* pl, void* p);
+// Temporaries of one build step, released when it goes out of scope.
+struct Scratch {
+  fmm_plan* pl;
+  std::vector<void*> ptrs;
+  explicit Scratch(fmm_plan* p) : pl(p) {}
+  void* get(size_t bytes) {
+    void* p = dev_alloc(pl, bytes);
+    ptrs.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    // the build's kernels may still read them: wait for the stream first
+    if (!ptrs.empty()) (void)hipStreamSynchronize(pl->alloc_stream);
+    for (void* p : ptrs) dev_free(pl, p);
+  }
+};
 
-// One tree inside a plan: depth, level offsets and first global box id.
+// One tree inside a plan: depth, level offsets, first global box id and
+// first global leaf.
 struct TreeDesc {
   int L;
   std::vector<int64_t> level_off;
   int64_t box_base;
+  int64_t leaf_base = 0;
 };
-// Leaf boxes and level steps over one or several trees (api.cpp).  M2M
-// step h takes the parents h+1 levels above each tree's leaves; L2L step l
-// takes level l of every tree at least that deep.  Boxes outside every M2L
-// pair and without such an ancestor are left out (their expansions are
-// never read, or are zero), except that every leaf gets its local.
-void make_steps(fmm_plan* pl, const std::vector<TreeDesc>& trees, hipStream_t st);
+// Leaf boxes and level steps of each side over its trees (api.cpp): side k
+// takes trees[k] (a plan with one side passes one group).  M2M step h takes
+// the parents h+1 levels above each tree's leaves; L2L step l takes level l
+// of every tree at least that deep.  Boxes outside every M2L pair and
+// without such an ancestor are left out (their expansions are never read,
+// or are zero), except that every leaf gets its local.  Also the boxes of
+// each list direction's target side whose local has no M2L pair.
+void make_steps(fmm_plan* pl, const std::vector<std::vector<TreeDesc>>& trees, hipStream_t st);
+// Side whose charges a pass in direction dir (0: G-hat, 1: G-hat^T) reads,
+// and side whose points it evaluates.
+inline const Side& src_side(const fmm_plan* pl, int dir) {
+  return pl->side[pl->nsides == 1 ? 0 : dir];
+}
+inline const Side& tgt_side(const fmm_plan* pl, int dir) {
+  return pl->side[pl->nsides == 1 ? 0 : 1 - dir];
+}
 // Union of independent plans (multi.hip): every per-point, per-box and
 // per-leaf array concatenated, indices shifted to global numbering.
-void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStream_t st);
+// With lists = false the sub-plans carry trees only, and perm stays local
+// to each sub-plan (input indices of its own point set).
+void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStream_t st,
+                 bool lists = true);
 
 // Tree build (tree.hip): fills perm, leaf_start, xs/ys/zs, centres, radii.
 void build_tree(fmm_plan* pl, const double* pos, hipStream_t st);
-// Lists (lists.hip): fills m2l_*, p2p_*, items.
-void build_lists(fmm_plan* pl, hipStream_t st);
+// Lists (lists.hip): fills m2l_*, p2p_*, items, from the level march
+// between the source tree src and the target tree tgt of the plan (the
+// same tree for a plan over one point set).
+void build_lists(fmm_plan* pl, const TreeDesc& src, const TreeDesc& tgt, hipStream_t st);
+// M2L work items and block segments of one list set from its CSR (lists.hip).
+void make_items(fmm_plan* pl, ListSet& S, hipStream_t st);
 // Operator tables for order p (tables.cpp), cached per process/device.
 const void* get_tables(int p, int precision, int device);
 // Evaluation (eval.hip): dir 0 = G-hat, dir 1 = G-hat^T.
-void evaluate(fmm_plan* pl, int dir, const void* q, int nrhs, void* pot, void* field,
-              hipStream_t st);
+void evaluate(fmm_plan* pl, const Workspace& ws, int dir, const void* q, int nrhs, void* pot,
+              void* field, hipStream_t st);
 // Up to batch_width() FP32 charge vectors in one pass (batch.hip).
 int batch_width();
 void evaluate_batch(fmm_plan* pl, int dir, const float* q, int R, float* pot, float* field,

@@ -1,7 +1,7 @@
 // Interaction lists by cross-level level marching (Sec. II.B).
 //
 // The working set of (source box, target box) pairs starts as
-// (root, root).  Each step refines one side -- the level with the larger
+// (root, root), itself tested first.  Each step refines one side -- the level with the larger
 // mean box radius, the source on equal means (or the target when the plan
 // asks for it), the other side once one side has reached the leaves -- by
 // replacing its box with each of its 2^s children, then moves every pair
@@ -11,7 +11,12 @@
 // are the direct (P2P) pairs.  Each step is one expand-test kernel, a
 // prefix scan of the verdicts and one compaction kernel; the host reads one
 // count per step to size the next.  Both lists are finally sorted by
-// (target, source) into CSR form.
+// (target, source) into CSR form.  Sources and targets may be two separate
+// trees of the plan (Sec. II.B, separate sources and targets): each side is
+// then refined by its own level-mean radii and stops at its own depth.
+// Same-level lists (the enumerated procedure at the start of Sec. II.B)
+// refine both sides in every step before testing, so boxes only meet boxes
+// of their own level.
 // The admissibility arithmetic must round like a plain IEEE evaluation in
 // the written order (no fused multiply-adds), so that the verdicts do not
 // depend on the compiler.
@@ -25,7 +30,7 @@
 namespace fmm {
 namespace {
 
-__global__ void k_expand_test(int64_t np, int nch, int refine_src,
+__global__ void k_expand_test(int64_t np, int nch, int refine_src, int test,
                               const int32_t* __restrict__ ps,
                               const int32_t* __restrict__ pt, int64_t off_s,
                               int64_t off_t, const double* __restrict__ cx,
@@ -57,7 +62,7 @@ __global__ void k_expand_test(int64_t np, int nch, int refine_src,
   double big = fmax(ra, rb), small = fmin(ra, rb);
   double lhs = big + theta * small;
   double rhs = theta * d;
-  adm[e] = (lhs <= rhs && d > 0.0) ? 1 : 0;
+  adm[e] = (test && lhs <= rhs && d > 0.0) ? 1 : 0;
 }
 
 __global__ void k_compact(int64_t ne, const int32_t* __restrict__ cs,
@@ -78,10 +83,10 @@ __global__ void k_compact(int64_t ne, const int32_t* __restrict__ cs,
 }
 
 __global__ void k_keys_from_pairs(int64_t np, const int32_t* __restrict__ ps,
-                                  const int32_t* __restrict__ pt,
-                                  uint64_t* __restrict__ keys) {
+                                  const int32_t* __restrict__ pt, int64_t leaf_s,
+                                  int64_t leaf_t, uint64_t* __restrict__ keys) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < np) keys[e] = ((uint64_t)pt[e] << 32) | (uint64_t)ps[e];
+  if (e < np) keys[e] = ((uint64_t)(leaf_t + pt[e]) << 32) | (uint64_t)(leaf_s + ps[e]);
 }
 
 // CSR from keys sorted by (target, source).
@@ -106,18 +111,6 @@ __global__ void k_csr(int64_t nk, const uint64_t* __restrict__ keys,
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-struct Scratch {
-  std::vector<void*> ptrs;
-  void* get(size_t bytes) {
-    void* p = nullptr;
-    FMM_HIP(hipMalloc(&p, std::max<size_t>(bytes, 16)));
-    ptrs.push_back(p);
-    return p;
-  }
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-};
 
 // (source << 32 | target) keys of a CSR list: the reversed pairs.
 __global__ void k_transposed_keys(int64_t ntgt, const int32_t* __restrict__ ptr,
@@ -151,104 +144,164 @@ void keys_to_csr(fmm_plan* pl, Scratch& sc, uint64_t* keys, int64_t nk,
   FMM_HIP(hipGetLastError());
 }
 
-// M2L work items of a list set: consecutive per target, each target's list
-// split into ceil(len / kItemPairs) items of equal length (+-1).  Shorter
-// items give more, more even work units (M2L runs one wave per SIMD, so the
-// last round of waves is what items of 16 leave unbalanced) at the price of
-// more partial rows for the sum before L2L; 12 measured best.
+}  // namespace
+
+// M2L work items of a list set, packed into blocks of kM2LBlock lanes so
+// that the items of one target always share a block (its partial sums are
+// then added inside the block, in lane order, and written once).  Each
+// target's list is split into ceil(len / kItemPairs) items of equal length
+// (+-1), at most kM2LBlock of them.  Blocks are filled first-fit from a
+// window of the next kPackWindow targets in box order, which keeps nearby
+// targets (and so their source boxes) in neighbouring blocks while leaving
+// few lanes idle; the lanes a block does not fill get target -1.
 void make_items(fmm_plan* pl, ListSet& S, hipStream_t st) {
-  const int kItemPairs = 12;
+  const int kItemPairs = 12, kPackWindow = 128;
   std::vector<int32_t> mptr(pl->nbox + 1);
   FMM_HIP(hipMemcpyAsync(mptr.data(), S.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
                          hipMemcpyDeviceToHost, st));
   FMM_HIP(hipStreamSynchronize(st));
-  std::vector<int32_t> it_t, it_b, it_e, it_ptr(pl->nbox + 1);
+  std::vector<int32_t> tg, ni;  // targets with a list, in box order; their item counts
   for (int64_t t = 0; t < pl->nbox; ++t) {
-    it_ptr[t] = (int32_t)it_t.size();
     const int32_t lt = mptr[t + 1] - mptr[t];
-    const int32_t ni = (lt + kItemPairs - 1) / kItemPairs;
-    for (int32_t j = 0; j < ni; ++j) {
-      it_t.push_back((int32_t)t);
-      it_b.push_back(mptr[t] + (int32_t)((int64_t)lt * j / ni));
-      it_e.push_back(mptr[t] + (int32_t)((int64_t)lt * (j + 1) / ni));
+    if (lt == 0) continue;
+    tg.push_back((int32_t)t);
+    ni.push_back(std::min((lt + kItemPairs - 1) / kItemPairs, kM2LBlock));
+  }
+  std::vector<int32_t> it_t, it_b, it_e, first(pl->nbox, 0), cnt(pl->nbox, 0);
+  std::vector<int32_t> seg_ptr(1, 0), seg_tgt, seg_lanes;
+  std::vector<char> placed(tg.size(), 0);
+  size_t j = 0;
+  while (j < tg.size()) {
+    int used = 0;
+    for (size_t k = j; k < tg.size() && k < j + kPackWindow && used < kM2LBlock; ++k) {
+      if (placed[k] || used + ni[k] > kM2LBlock) continue;
+      placed[k] = 1;
+      const int32_t t = tg[k], lt = mptr[t + 1] - mptr[t];
+      first[t] = (int32_t)it_t.size();
+      cnt[t] = ni[k];
+      seg_tgt.push_back(t);
+      seg_lanes.push_back(used | ((used + ni[k]) << 8));
+      for (int32_t q = 0; q < ni[k]; ++q) {
+        it_t.push_back(t);
+        it_b.push_back(mptr[t] + (int32_t)((int64_t)lt * q / ni[k]));
+        it_e.push_back(mptr[t] + (int32_t)((int64_t)lt * (q + 1) / ni[k]));
+      }
+      used += ni[k];
     }
+    for (; used < kM2LBlock; ++used) {
+      it_t.push_back(-1);
+      it_b.push_back(0);
+      it_e.push_back(0);
+    }
+    seg_ptr.push_back((int32_t)seg_tgt.size());
+    while (j < tg.size() && placed[j]) ++j;
   }
-  it_ptr[pl->nbox] = (int32_t)it_t.size();
   S.n_items = (int64_t)it_t.size();
-  const size_t ni = std::max<size_t>(it_t.size(), 1);
-  S.item_tgt = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  S.item_begin = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  S.item_end = (int32_t*)plan_alloc(pl, sizeof(int32_t) * ni);
-  S.item_ptr = (int32_t*)plan_alloc(pl, sizeof(int32_t) * (pl->nbox + 1));
-  if (!it_t.empty()) {
-    FMM_HIP(hipMemcpyAsync(S.item_tgt, it_t.data(), sizeof(int32_t) * it_t.size(),
-                           hipMemcpyHostToDevice, st));
-    FMM_HIP(hipMemcpyAsync(S.item_begin, it_b.data(), sizeof(int32_t) * it_b.size(),
-                           hipMemcpyHostToDevice, st));
-    FMM_HIP(hipMemcpyAsync(S.item_end, it_e.data(), sizeof(int32_t) * it_e.size(),
-                           hipMemcpyHostToDevice, st));
-  }
-  FMM_HIP(hipMemcpyAsync(S.item_ptr, it_ptr.data(), sizeof(int32_t) * it_ptr.size(),
-                         hipMemcpyHostToDevice, st));
+  S.n_blocks = S.n_items / kM2LBlock;
+  auto up = [&](const std::vector<int32_t>& v) {
+    int32_t* d = (int32_t*)plan_alloc(pl, sizeof(int32_t) * std::max<size_t>(v.size(), 1));
+    if (!v.empty())
+      FMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st));
+    return d;
+  };
+  S.item_tgt = up(it_t);
+  S.item_begin = up(it_b);
+  S.item_end = up(it_e);
+  S.item_first = up(first);
+  S.item_cnt = up(cnt);
+  S.seg_ptr = up(seg_ptr);
+  S.seg_tgt = up(seg_tgt);
+  S.seg_lanes = up(seg_lanes);
   FMM_HIP(hipStreamSynchronize(st));
 }
 
-}  // namespace
-
-void build_lists(fmm_plan* pl, hipStream_t st) {
-  const int L = pl->L, nch = pl->nch;
+void build_lists(fmm_plan* pl, const TreeDesc& ts, const TreeDesc& tt, hipStream_t st) {
+  const int Ls = ts.L, Lt = tt.L, nch = pl->nch;
   const int T = 256;
-  Scratch sc;
+  Scratch sc(pl);
   // level-mean radii, summed in box order on the host
   std::vector<double> rad(pl->nbox);
   FMM_HIP(hipMemcpyAsync(rad.data(), pl->radius, sizeof(double) * pl->nbox,
                          hipMemcpyDeviceToHost, st));
   FMM_HIP(hipStreamSynchronize(st));
   // Length scale of each box's expansions: its radius, floored at 2^-30 of
-  // the root radius (boxes whose points coincide have radius 0).
+  // its tree's root radius (boxes whose points coincide have radius 0).
   {
-    const double floor_r = rad[0] > 0.0 ? std::ldexp(rad[0], -30) : 1.0;
-    std::vector<double> scl(pl->nbox);
-    for (int64_t b = 0; b < pl->nbox; ++b) scl[b] = std::max(rad[b], floor_r);
+    std::vector<double> scl(rad);
+    for (const TreeDesc* t : {&ts, &tt}) {
+      const double r0 = rad[t->box_base];
+      const double floor_r = r0 > 0.0 ? std::ldexp(r0, -30) : 1.0;
+      for (int64_t b = t->box_base; b < t->box_base + t->level_off[t->L + 1]; ++b)
+        scl[b] = std::max(rad[b], floor_r);
+    }
     FMM_HIP(hipMemcpyAsync(pl->scale, scl.data(), sizeof(double) * pl->nbox,
                            hipMemcpyHostToDevice, st));
     FMM_HIP(hipStreamSynchronize(st));
   }
-  std::vector<double> avg(L + 1);
-  for (int l = 0; l <= L; ++l) {
-    double acc = 0.0;
-    for (int64_t b = pl->level_off[l]; b < pl->level_off[l + 1]; ++b) acc += rad[b];
-    avg[l] = acc / (double)(pl->level_off[l + 1] - pl->level_off[l]);
-  }
+  auto level_means = [&](const TreeDesc& t) {
+    std::vector<double> avg(t.L + 1);
+    for (int l = 0; l <= t.L; ++l) {
+      double acc = 0.0;
+      for (int64_t b = t.level_off[l]; b < t.level_off[l + 1]; ++b) acc += rad[t.box_base + b];
+      avg[l] = acc / (double)(t.level_off[l + 1] - t.level_off[l]);
+    }
+    return avg;
+  };
+  const std::vector<double> avg_s = level_means(ts), avg_t = level_means(tt);
 
+  std::vector<std::pair<uint64_t*, int64_t>> m2l_parts;
+  int64_t n_m2l = 0;
+  int64_t np = 1;
+  // The march starts with the pair of roots; two separate hierarchies may be
+  // well separated as a whole (with one tree the roots coincide, d = 0, and
+  // never are).  Tested on the host in the kernel's arithmetic order.
+  {
+    std::vector<double> c(6);
+    for (int a = 0; a < 3; ++a) {
+      double* arr[3] = {pl->cx, pl->cy, pl->cz};
+      FMM_HIP(hipMemcpyAsync(&c[a], arr[a] + ts.box_base, sizeof(double), hipMemcpyDeviceToHost, st));
+      FMM_HIP(hipMemcpyAsync(&c[3 + a], arr[a] + tt.box_base, sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    }
+    FMM_HIP(hipStreamSynchronize(st));
+    double dx = c[0] - c[3];
+    double dy = c[1] - c[4];
+    double dz = c[2] - c[5];
+    double d2 = dx * dx;
+    d2 = d2 + dy * dy;
+    d2 = d2 + dz * dz;
+    const double d = std::sqrt(d2);
+    const double ra = rad[ts.box_base], rb = rad[tt.box_base];
+    const double big = std::fmax(ra, rb), small = std::fmin(ra, rb);
+    const double lhs = big + pl->prm.theta * small;
+    const double rhs = pl->prm.theta * d;
+    if (lhs <= rhs && d > 0.0) {
+      uint64_t* k = (uint64_t*)sc.get(sizeof(uint64_t));
+      const uint64_t key = ((uint64_t)tt.box_base << 32) | (uint64_t)ts.box_base;
+      FMM_HIP(hipMemcpyAsync(k, &key, sizeof(uint64_t), hipMemcpyHostToDevice, st));
+      FMM_HIP(hipStreamSynchronize(st));
+      m2l_parts.emplace_back(k, 1);
+      n_m2l = 1;
+      np = 0;
+    }
+  }
   int32_t* ps = (int32_t*)sc.get(sizeof(int32_t));
   int32_t* pt = (int32_t*)sc.get(sizeof(int32_t));
   FMM_HIP(hipMemsetAsync(ps, 0, sizeof(int32_t), st));
   FMM_HIP(hipMemsetAsync(pt, 0, sizeof(int32_t), st));
-  int64_t np = 1;
   int ls = 0, lt = 0;
-  std::vector<std::pair<uint64_t*, int64_t>> m2l_parts;
-  int64_t n_m2l = 0;
-  while (np > 0 && !(ls == L && lt == L)) {
-    bool src_side;
-    if (ls == L)
-      src_side = false;
-    else if (lt == L)
-      src_side = true;
-    else if (avg[ls] > avg[lt])
-      src_side = true;
-    else if (avg[ls] < avg[lt])
-      src_side = false;
-    else
-      src_side = pl->prm.tie_refine == FMM_TIE_SOURCE;
+  // One refinement of one side; with test, admissible pairs leave the
+  // working set for the M2L list.
+  auto step = [&](bool src_side, bool test) {
     if (src_side) ++ls; else ++lt;
     const int64_t ne = np * nch;
     int32_t* cs = (int32_t*)sc.get(sizeof(int32_t) * ne);
     int32_t* ct = (int32_t*)sc.get(sizeof(int32_t) * ne);
     int32_t* adm = (int32_t*)sc.get(sizeof(int32_t) * ne);
     int32_t* excl = (int32_t*)sc.get(sizeof(int32_t) * ne);
+    const int64_t off_s = ts.box_base + ts.level_off[ls], off_t = tt.box_base + tt.level_off[lt];
     k_expand_test<<<blocks(ne, T), T, 0, st>>>(
-        np, nch, src_side ? 1 : 0, ps, pt, pl->level_off[ls], pl->level_off[lt],
+        np, nch, src_side ? 1 : 0, test ? 1 : 0, ps, pt, off_s, off_t,
         pl->cx, pl->cy, pl->cz, pl->radius, pl->prm.theta, cs, ct, adm);
     FMM_HIP(hipGetLastError());
     size_t tb = scan_i32_temp(ne);
@@ -262,14 +315,34 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
     uint64_t* keys = (uint64_t*)sc.get(sizeof(uint64_t) * std::max<int64_t>(nadm, 1));
     int32_t* ns = (int32_t*)sc.get(sizeof(int32_t) * std::max<int64_t>(ne - nadm, 1));
     int32_t* nt = (int32_t*)sc.get(sizeof(int32_t) * std::max<int64_t>(ne - nadm, 1));
-    k_compact<<<blocks(ne, T), T, 0, st>>>(ne, cs, ct, adm, excl, pl->level_off[ls],
-                                           pl->level_off[lt], keys, ns, nt);
+    k_compact<<<blocks(ne, T), T, 0, st>>>(ne, cs, ct, adm, excl, off_s, off_t, keys, ns, nt);
     FMM_HIP(hipGetLastError());
     if (nadm > 0) m2l_parts.emplace_back(keys, nadm);
     n_m2l += nadm;
     ps = ns;
     pt = nt;
     np = ne - nadm;
+  };
+  const bool same_level = pl->prm.lists == FMM_LISTS_SAME_LEVEL;
+  while (np > 0 && !(ls == Ls && lt == Lt)) {
+    if (same_level && ls < Ls && lt < Lt) {
+      // same-level lists: both sides advance, then the pairs are tested
+      step(true, false);
+      step(false, true);
+      continue;
+    }
+    bool src_side;
+    if (ls == Ls)
+      src_side = false;
+    else if (lt == Lt)
+      src_side = true;
+    else if (avg_s[ls] > avg_t[lt])
+      src_side = true;
+    else if (avg_s[ls] < avg_t[lt])
+      src_side = false;
+    else
+      src_side = pl->prm.tie_refine == FMM_TIE_SOURCE;
+    step(src_side, true);
   }
   // M2L CSR over all target boxes
   uint64_t* all = (uint64_t*)sc.get(sizeof(uint64_t) * std::max<int64_t>(n_m2l, 1));
@@ -283,11 +356,12 @@ void build_lists(fmm_plan* pl, hipStream_t st) {
   ListSet& A = pl->lists[1];
   keys_to_csr(pl, sc, all, n_m2l, pl->nbox, &F.m2l_src, &F.m2l_ptr, st);
   F.n_m2l = A.n_m2l = n_m2l;
-  // P2P CSR over leaves (what is left once both sides reached the leaves)
-  if (!(ls == L && lt == L)) np = 0;
+  // P2P CSR over leaves (what is left once both sides reached the leaves),
+  // leaves numbered globally
+  if (!(ls == Ls && lt == Lt)) np = 0;
   uint64_t* pk = (uint64_t*)sc.get(sizeof(uint64_t) * std::max<int64_t>(np, 1));
   if (np > 0) {
-    k_keys_from_pairs<<<blocks(np, T), T, 0, st>>>(np, ps, pt, pk);
+    k_keys_from_pairs<<<blocks(np, T), T, 0, st>>>(np, ps, pt, ts.leaf_base, tt.leaf_base, pk);
     FMM_HIP(hipGetLastError());
   }
   keys_to_csr(pl, sc, pk, np, pl->nleaf, &F.p2p_src, &F.p2p_ptr, st);

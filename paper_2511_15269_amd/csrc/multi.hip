@@ -2,9 +2,10 @@
 //
 // Each problem keeps its own tree and lists (built exactly as for a single
 // plan).  The union concatenates every per-point, per-box and per-leaf array
-// in problem order and shifts the indices stored in them (point, box, leaf,
-// list-pair and work-item ids) by the running totals, so that every
-// evaluation stage runs as one launch over the work of all problems.
+// in problem order and shifts the indices stored in them (point, box, leaf
+// and list-pair ids) by the running totals, so that every evaluation stage
+// runs as one launch over the work of all problems; the M2L work items are
+// then packed over the union's lists.
 #include <algorithm>
 
 #include "internal.h"
@@ -34,7 +35,8 @@ void copy_plain(T* dst, const T* src, int64_t n, hipStream_t st) {
 
 }  // namespace
 
-void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStream_t st) {
+void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStream_t st,
+                 bool lists) {
   const fmm_plan* f = subs.front();
   U->device = f->device;
   U->prm = f->prm;
@@ -48,7 +50,7 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
   U->p2p_inter = 0;
   U->max_leaf_count = 0;
   U->has_dup = false;
-  int64_t n_m2l[2] = {0, 0}, n_p2p[2] = {0, 0}, n_items[2] = {0, 0};
+  int64_t n_m2l[2] = {0, 0}, n_p2p[2] = {0, 0};
   for (const fmm_plan* p : subs) {
     U->n += p->n;
     U->nbox += p->nbox;
@@ -60,7 +62,6 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
     for (int d = 0; d < 2; ++d) {
       n_m2l[d] += p->lists[d].n_m2l;
       n_p2p[d] += p->lists[d].n_p2p;
-      n_items[d] += p->lists[d].n_items;
     }
   }
   if (U->n >= ((int64_t)1 << 31) || U->nbox >= ((int64_t)1 << 31))
@@ -80,25 +81,20 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
   U->cz = f64(U->nbox);
   U->radius = f64(U->nbox);
   U->scale = f64(U->nbox);
-  for (int d = 0; d < 2; ++d) {
+  for (int d = 0; d < 2 && lists; ++d) {
     ListSet& S = U->lists[d];
     S.n_m2l = n_m2l[d];
     S.n_p2p = n_p2p[d];
-    S.n_items = n_items[d];
     S.m2l_ptr = i32(U->nbox + 1);
     S.m2l_src = i32(std::max<int64_t>(S.n_m2l, 1));
     S.p2p_ptr = i32(U->nleaf + 1);
     S.p2p_src = i32(std::max<int64_t>(S.n_p2p, 1));
-    S.item_tgt = i32(std::max<int64_t>(S.n_items, 1));
-    S.item_begin = i32(std::max<int64_t>(S.n_items, 1));
-    S.item_end = i32(std::max<int64_t>(S.n_items, 1));
-    S.item_ptr = i32(U->nbox + 1);
   }
 
   int64_t pb = 0, bb = 0, lb = 0;
-  int64_t mb[2] = {0, 0}, qb[2] = {0, 0}, ib[2] = {0, 0};
+  int64_t mb[2] = {0, 0}, qb[2] = {0, 0};
   for (const fmm_plan* p : subs) {
-    copy_shifted(U->perm + pb, p->perm, p->n, pb, st);
+    copy_shifted(U->perm + pb, p->perm, p->n, lists ? pb : 0, st);
     // n+1 entries: the last one equals the next problem's first after the
     // shift and is overwritten by it in stream order.
     copy_shifted(U->leaf_start + lb, p->leaf_start, p->nleaf + 1, pb, st);
@@ -110,26 +106,26 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
     copy_plain(U->cz + bb, p->cz, p->nbox, st);
     copy_plain(U->radius + bb, p->radius, p->nbox, st);
     copy_plain(U->scale + bb, p->scale, p->nbox, st);
-    for (int d = 0; d < 2; ++d) {
+    for (int d = 0; d < 2 && lists; ++d) {
       const ListSet& A = p->lists[d];
       ListSet& S = U->lists[d];
       copy_shifted(S.m2l_ptr + bb, A.m2l_ptr, p->nbox + 1, mb[d], st);
       copy_shifted(S.m2l_src + mb[d], A.m2l_src, A.n_m2l, bb, st);
       copy_shifted(S.p2p_ptr + lb, A.p2p_ptr, p->nleaf + 1, qb[d], st);
       copy_shifted(S.p2p_src + qb[d], A.p2p_src, A.n_p2p, lb, st);
-      copy_shifted(S.item_tgt + ib[d], A.item_tgt, A.n_items, bb, st);
-      copy_shifted(S.item_begin + ib[d], A.item_begin, A.n_items, mb[d], st);
-      copy_shifted(S.item_end + ib[d], A.item_end, A.n_items, mb[d], st);
-      copy_shifted(S.item_ptr + bb, A.item_ptr, p->nbox + 1, ib[d], st);
       mb[d] += A.n_m2l;
       qb[d] += A.n_p2p;
-      ib[d] += A.n_items;
     }
     pb += p->n;
     bb += p->nbox;
     lb += p->nleaf;
   }
   FMM_HIP(hipStreamSynchronize(st));
+  if (!lists) return;
+  // M2L work items over the union's lists: blocks may then mix targets of
+  // different problems
+  make_items(U, U->lists[0], st);
+  make_items(U, U->lists[1], st);
 }
 
 }  // namespace fmm

@@ -464,10 +464,10 @@ __device__ __forceinline__ float inv_sqrt(float r2) { return __builtin_amdgcn_rs
 // level-by-level L2L kernels then add the translated parent local.
 template <typename T>
 __global__ void k_psum(int64_t nb, const int32_t* __restrict__ boxes,
-                       const int32_t* __restrict__ item_ptr, const T* __restrict__ partial,
-                       int W, T* __restrict__ D) {
+                       const int32_t* __restrict__ item_first, const int32_t* __restrict__ item_cnt,
+                       const T* __restrict__ partial, int W, T* __restrict__ D) {
   const int64_t t = boxes[blockIdx.x];
-  const int b = item_ptr[t], e = item_ptr[t + 1];
+  const int b = item_first[t], e = b + item_cnt[t];
   for (int k = threadIdx.x; k < W; k += blockDim.x) {
     T acc = T(0);
     int it = b;

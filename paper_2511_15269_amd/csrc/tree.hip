@@ -183,27 +183,13 @@ __global__ void k_dup_check(int n, const uint64_t* __restrict__ h, const int32_t
   }
 }
 
-// Temporary device memory released when the build ends.
-struct Scratch {
-  std::vector<void*> ptrs;
-  void* get(size_t bytes) {
-    void* p = nullptr;
-    FMM_HIP(hipMalloc(&p, std::max<size_t>(bytes, 16)));
-    ptrs.push_back(p);
-    return p;
-  }
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-};
-
 }  // namespace
 
 void build_tree(fmm_plan* pl, const double* pos, hipStream_t st) {
   const int n = (int)pl->n;
   const int L = pl->L, s = pl->s;
   const int T = 256;
-  Scratch sc;
+  Scratch sc(pl);
   double* X = (double*)sc.get(sizeof(double) * 3 * (size_t)n);
   uint64_t* keys = (uint64_t*)sc.get(sizeof(uint64_t) * 3 * (size_t)n);
   uint64_t* keys_out = (uint64_t*)sc.get(sizeof(uint64_t) * (size_t)n);

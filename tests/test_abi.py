@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert L.lib().fmm_abi_version() == 1
+    assert L.lib().fmm_abi_version() == 2
 
 
 def _create(**kw):
@@ -47,12 +47,14 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(p=0), L.FMM_EINVAL), (dict(p=11), L.FMM_ENOTSUP), (dict(splits=0), L.FMM_EINVAL),
+    (dict(p=-1), L.FMM_EINVAL), (dict(p=0), L.FMM_ENOTSUP), (dict(p=11), L.FMM_ENOTSUP),
+    (dict(p=20), L.FMM_ENOTSUP), (dict(splits=0), L.FMM_EINVAL),
     (dict(splits=4), L.FMM_EINVAL), (dict(leaf_max=3), L.FMM_EINVAL), (dict(theta=0.0), L.FMM_EINVAL),
     (dict(theta=1.0), L.FMM_EINVAL), (dict(theta=float("nan")), L.FMM_EINVAL),
     (dict(max_depth=-1), L.FMM_EINVAL), (dict(max_depth=17), L.FMM_EINVAL),
     (dict(precision=2), L.FMM_EINVAL), (dict(tie_refine=2), L.FMM_EINVAL),
-    (dict(max_rhs=0), L.FMM_EINVAL), (dict(n=0), L.FMM_EINVAL), (dict(n=1 << 31), L.FMM_EINVAL)])
+    (dict(max_rhs=0), L.FMM_EINVAL), (dict(n=0), L.FMM_EINVAL), (dict(n=1 << 31), L.FMM_EINVAL),
+    (dict(lists=2), L.FMM_EINVAL), (dict(lists=-1), L.FMM_EINVAL)])
 def test_bad_parameters_are_rejected_and_out_is_untouched(kw, code):
     st, out = _create(**kw)
     assert st == code
@@ -106,3 +108,91 @@ def test_graph_null_arguments():
 def test_autotune_null_arguments():
     lib = L.lib()
     assert lib.fmm_plan_autotune(None, None, None, None, None) == L.FMM_EINVAL
+
+
+def _prm(**kw):
+    prm = L.FmmParams(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16,
+                      precision=L.FMM_FP64, tie_refine=0, max_rhs=1)
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return prm
+
+
+def _expected_workspace(n, p, leaf, s, max_depth, es, batched):
+    """Workspace of a plan of n points, from the layout fmm.h documents:
+    nbox = sum_{l<=L} 2^{s l} with L the smallest depth whose leaves hold at
+    most leaf points; buffers rounded up to 256 bytes each."""
+    L = 0
+    while L < max_depth and -(-n // (1 << (s * L))) > leaf:
+        L += 1
+    nbox = sum(1 << (s * l) for l in range(L + 1))
+    K = (p + 1) ** 2
+    sizes = [32 * n, es * K * nbox, es * K * nbox, 4 * es * n, 3 * es * n]
+    if batched:
+        sizes += [128 * n, 128 * K * nbox, 128 * K * nbox, 128 * n, 384 * n]
+    return sum(-(-b // 256) * 256 for b in sizes)
+
+
+@pytest.mark.parametrize("n,p,leaf,s,prec,rhs", [
+    (1, 1, 8, 3, L.FMM_FP64, 1), (4096, 6, 64, 2, L.FMM_FP64, 1),
+    (1 << 20, 8, 128, 3, L.FMM_FP64, 1), (1 << 20, 8, 128, 3, L.FMM_FP32, 1),
+    (1 << 18, 8, 128, 3, L.FMM_FP32, 32), (1 << 18, 8, 128, 3, L.FMM_FP64, 32),
+    (100001, 10, 40, 1, L.FMM_FP32, 1), (3000, 5, 2, 1, L.FMM_FP64, 1)])
+def test_workspace_bytes_query(n, p, leaf, s, prec, rhs):
+    out = ctypes.c_int64(-1)
+    prm = _prm(p=p, leaf_max=leaf, splits=s, precision=prec, max_rhs=rhs)
+    assert L.lib().fmm_plan_workspace_bytes(n, ctypes.byref(prm), ctypes.byref(out)) == L.FMM_OK
+    es = 4 if prec == L.FMM_FP32 else 8
+    want = _expected_workspace(n, p, leaf, s, 16, es, prec == L.FMM_FP32 and rhs > 1)
+    assert out.value == want
+
+
+def test_workspace_bytes_rejects_what_create_rejects():
+    out = ctypes.c_int64(7)
+    lib = L.lib()
+    assert lib.fmm_plan_workspace_bytes(0, ctypes.byref(_prm()), ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_workspace_bytes(10, None, ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_workspace_bytes(10, ctypes.byref(_prm()), None) == L.FMM_EINVAL
+    assert lib.fmm_plan_workspace_bytes(10, ctypes.byref(_prm(p=11)), ctypes.byref(out)) == L.FMM_ENOTSUP
+    assert out.value == 7
+
+
+def test_create_ex_checks_the_allocator_and_flags_first():
+    lib = L.lib()
+    calls = []
+    alloc = L.ALLOC_FN(lambda ctx, n, st: calls.append(n) or None)
+    free = L.FREE_FN(lambda ctx, p, st: calls.append(p))
+    half = L.FmmAllocator(alloc, L.FREE_FN(), None)  # no free callback
+    out = ctypes.c_void_p(99)
+    prm = _prm()
+    st = lib.fmm_plan_create_ex(ctypes.c_void_p(0x1000), 100, ctypes.byref(prm), ctypes.byref(half),
+                                0, None, ctypes.byref(out))
+    assert st == L.FMM_EINVAL and out.value == 99
+    full = L.FmmAllocator(alloc, free, None)
+    st = lib.fmm_plan_create_ex(ctypes.c_void_p(0x1000), 100, ctypes.byref(prm), ctypes.byref(full),
+                                8, None, ctypes.byref(out))
+    assert st == L.FMM_EINVAL and out.value == 99
+    st = lib.fmm_plan_create_ex(ctypes.c_void_p(0x1000), 0, ctypes.byref(prm), ctypes.byref(full),
+                                0, None, ctypes.byref(out))
+    assert st == L.FMM_EINVAL and out.value == 99
+    assert calls == []  # rejected before any allocation
+
+
+def test_create_st_checks_arguments_first():
+    lib = L.lib()
+    out = ctypes.c_void_p(55)
+    prm = _prm()
+    d = ctypes.c_void_p(0x1000)
+    assert lib.fmm_plan_create_st(None, 10, d, 10, ctypes.byref(prm), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_create_st(d, 10, None, 10, ctypes.byref(prm), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_create_st(d, 0, d, 10, ctypes.byref(prm), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_create_st(d, 10, d, 0, ctypes.byref(prm), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_create_st(d, 1 << 30, d, 1 << 30, ctypes.byref(prm), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_EINVAL
+    assert lib.fmm_plan_create_st(d, 10, d, 10, ctypes.byref(_prm(p=12)), None, 0, None,
+                                  ctypes.byref(out)) == L.FMM_ENOTSUP
+    assert out.value == 55

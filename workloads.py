@@ -19,6 +19,14 @@ Plummer sets below are synthetic stress cases of the same method):
                            the cumulative mass profile), isotropic directions,
                            charges in (0,1]
 * ``uneven_problem_sizes`` -- problem sizes log-uniform in [1e4, 5e5]
+* ``sphere_surface``    -- positions uniform on a sphere surface (the
+                           paper's second distribution, Sec. III.A),
+                           charges U[-1,1)
+* ``shielding``         -- the active-shielding geometry of Sec. III.B:
+                           128 shield charges spaced regularly on a sphere of
+                           radius 2, 256 external charges of random position
+                           on a sphere of radius 5 and random charge, 1024
+                           probes evenly on radius 1.5 and 1024 on radius 2.5
 """
 from __future__ import annotations
 
@@ -32,6 +40,9 @@ __all__ = [
     "plummer",
     "uneven_problem_sizes",
     "sample_targets",
+    "sphere_surface",
+    "fibonacci_sphere",
+    "shielding",
     "WORKLOADS",
 ]
 
@@ -89,6 +100,40 @@ def plummer(n: int, seed: int = 0, a: float = 0.1):
     pos = r[:, None] * d
     q = 1.0 - rng.random(n)
     return pos, q
+
+
+def sphere_surface(n: int, seed: int = 0, radius: float = 1.0, centre=(0.0, 0.0, 0.0)):
+    """Positions uniform on the sphere |x - centre| = radius (normalised
+    standard normal vectors), charges uniform in [-1, 1)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    pos = np.asarray(centre, dtype=np.float64) + radius * v
+    q = rng.uniform(-1.0, 1.0, n)
+    return pos, q
+
+
+def fibonacci_sphere(n: int, radius: float = 1.0):
+    """``n`` points spread evenly over a sphere of the given radius (the
+    golden-angle spiral: equal-area bands in z, azimuth advanced by the
+    golden angle)."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / n
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = k * (math.pi * (3.0 - math.sqrt(5.0)))
+    return radius * np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
+
+
+def shielding(seed: int = 0, n_sh: int = 128, n_ext: int = 256, n_in: int = 1024,
+              n_out: int = 1024, r_sh: float = 2.0, r_ext: float = 5.0, r_in: float = 1.5,
+              r_out: float = 2.5):
+    """Geometry of the active-shielding example (Sec. III.B): shield charge
+    positions (regular on radius r_sh), external charges (uniformly random
+    positions on radius r_ext, charges U[-1,1)), inner and outer probe
+    points (even on radii r_in and r_out).  Shield charges start at zero."""
+    ext_pos, ext_q = sphere_surface(n_ext, seed, r_ext)
+    return dict(shield=fibonacci_sphere(n_sh, r_sh), ext=ext_pos, q_ext=ext_q,
+                inner=fibonacci_sphere(n_in, r_in), outer=fibonacci_sphere(n_out, r_out))
 
 
 def uneven_problem_sizes(k: int = 16, seed: int = 100, lo: float = 1e4,

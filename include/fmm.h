@@ -146,10 +146,17 @@ const char* fmm_last_error(void);
 fmm_status fmm_plan_create(const double* pos, int64_t n, const fmm_params* prm,
                            void* stream, fmm_plan** out);
 
+/* Plan flag (fmm_plan_create_ex, fmm_multi_plan_create_ex,
+ * fmm_plan_create_st): hold no evaluation workspace.  Such a plan keeps only
+ * its tree and lists; it is evaluated with fmm_evaluate_noalloc, and
+ * fmm_evaluate, fmm_evaluate_transposed, fmm_adjoint, fmm_graph_create and
+ * fmm_plan_autotune return FMM_ESTATE on it. */
+#define FMM_PLAN_NO_WORKSPACE 1u
+
 /* fmm_plan_create with the plan's device memory taken from `allocator`
- * (NULL: hipMalloc/hipFree).  flags must be 0.  Errors: as
+ * (NULL: hipMalloc/hipFree).  flags: 0 or FMM_PLAN_NO_WORKSPACE.  Errors: as
  * fmm_plan_create, plus FMM_EINVAL for an allocator without both
- * callbacks, unknown flags or a block not aligned to 256 bytes, and
+ * callbacks, other flags or a block not aligned to 256 bytes, and
  * FMM_ENOMEM when alloc returns NULL (everything allocated so far is
  * returned through free). */
 fmm_status fmm_plan_create_ex(const double* pos, int64_t n, const fmm_params* prm,
@@ -240,6 +247,27 @@ fmm_status fmm_plan_get_info(const fmm_plan* plan, fmm_plan_info* info);
  * Errors: FMM_EINVAL (NULL q or pot, nrhs out of range), FMM_EDEVICE. */
 fmm_status fmm_evaluate(fmm_plan* plan, const void* q, int nrhs, void* pot,
                         void* field, void* stream);
+
+/* fmm_evaluate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * evaluation workspace of each pass -- source records, multipole and local
+ * expansions, near field -- comes from one device array of
+ * FMM_NOALLOC_MAX_BYTES that the library holds on every device it runs on
+ * until the process ends, shared by all plans, instead of from the plan.
+ * Nothing is allocated (the array's address is looked up once per device,
+ * on the first call there).  The plan may be one created with
+ * FMM_PLAN_NO_WORKSPACE.  Arguments, results and errors as fmm_evaluate;
+ * charge vectors are evaluated one pass each; stage profiling is not
+ * recorded.  Plans whose pass needs more than FMM_NOALLOC_MAX_BYTES
+ * (32 n + 2 nbox (p+1)^2 e + 4 n e bytes, e = 8 for FP64 and 4 for FP32,
+ * each part rounded up to 256) are rejected with FMM_EINVAL.  Every call on
+ * a device uses the same array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  Each
+ * pass writes every part of the array it reads before reading it, so the
+ * contents a previous call left do not matter. */
+#define FMM_NOALLOC_MAX_BYTES (128u << 20)
+fmm_status fmm_evaluate_noalloc(fmm_plan* plan, const void* q, int nrhs, void* pot,
+                                void* field, void* stream);
 
 /* Transposed evaluation: the adjoint operator G-hat^T of fmm_evaluate's
  * linear map q -> u-hat (tree, lists and centres frozen), i.e. the same FMM

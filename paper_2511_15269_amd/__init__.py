@@ -17,7 +17,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (ALLOC_FN, FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_TIE_SOURCE, FMM_TIE_TARGET,
+from ._lib import (ALLOC_FN, FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_PLAN_NO_WORKSPACE,
+                   FMM_TIE_SOURCE, FMM_TIE_TARGET,
                    FREE_FN, STAGES, FmmAllocator, FMMError, FmmParams, FmmPlanInfo, check, lib)
 
 __all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotential",
@@ -136,7 +137,7 @@ class Plan:
 
     def __init__(self, pos: torch.Tensor, p=8, leaf_max=128, splits=2, theta=0.7,
                  max_depth=16, precision="fp64", tie="source", max_rhs=1, stream=None,
-                 sizes=None, allocator=None, targets=None, lists="cross"):
+                 sizes=None, allocator=None, targets=None, lists="cross", workspace=True):
         if not (isinstance(pos, torch.Tensor) and pos.is_cuda):
             raise ValueError("pos must be a CUDA tensor")
         if pos.dim() != 2 or pos.shape[1] != 3:
@@ -156,6 +157,9 @@ class Plan:
             allocator = torch_allocator(self.device)
         self._alloc = allocator
         ap = ctypes.byref(allocator) if allocator is not None else None
+        # workspace=False: the plan holds tree and lists only and is
+        # evaluated with evaluate_noalloc (FMM_PLAN_NO_WORKSPACE)
+        flags = 0 if workspace else FMM_PLAN_NO_WORKSPACE
         with torch.cuda.device(self.device):
             if targets is not None:
                 if sizes is not None:
@@ -169,11 +173,11 @@ class Plan:
                 self.n_out = tgt.shape[0]
                 check(lib().fmm_plan_create_st(ctypes.c_void_p(pos.data_ptr()), self.n,
                                                ctypes.c_void_p(tgt.data_ptr()), self.n_out,
-                                               ctypes.byref(self._prm), ap, 0,
+                                               ctypes.byref(self._prm), ap, flags,
                                                _stream_ptr(stream), ctypes.byref(self._h)))
             elif sizes is None:
                 check(lib().fmm_plan_create_ex(ctypes.c_void_p(pos.data_ptr()), self.n,
-                                               ctypes.byref(self._prm), ap, 0,
+                                               ctypes.byref(self._prm), ap, flags,
                                                _stream_ptr(stream), ctypes.byref(self._h)))
             else:
                 off = np.concatenate([[0], np.cumsum(np.asarray(sizes, np.int64))])
@@ -183,7 +187,8 @@ class Plan:
                 check(lib().fmm_multi_plan_create_ex(
                     ctypes.c_void_p(pos.data_ptr()),
                     off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
-                    ctypes.byref(self._prm), ap, 0, _stream_ptr(stream), ctypes.byref(self._h)))
+                    ctypes.byref(self._prm), ap, flags, _stream_ptr(stream),
+                    ctypes.byref(self._h)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -286,6 +291,24 @@ class Plan:
         if single:
             return pot[0], (fld[0] if fld is not None else None)
         return pot, fld
+
+    def evaluate_noalloc(self, q: torch.Tensor, out, stream=None) -> None:
+        """evaluate into caller buffers ``out`` = (pot [R, M], field
+        [R, M, 3] or None) with the library's static workspace
+        (fmm_evaluate_noalloc): the call allocates nothing, also not here."""
+        qq = self._vec(q, "q")
+        R = qq.shape[0]
+        if qq.data_ptr() != q.data_ptr():
+            raise ValueError("q must be contiguous")
+        pot, fld = out
+        _check_out(pot, (R, self.n_out), self.dtype, self.device, "out[0] (pot)")
+        if fld is not None:
+            _check_out(fld, (R, self.n_out, 3), self.dtype, self.device, "out[1] (field)")
+        with torch.cuda.device(self.device):
+            check(lib().fmm_evaluate_noalloc(self._h, ctypes.c_void_p(qq.data_ptr()), R,
+                                             ctypes.c_void_p(pot.data_ptr()),
+                                             ctypes.c_void_p(fld.data_ptr()) if fld is not None
+                                             else None, _stream_ptr(stream)))
 
     def autotune(self, q: torch.Tensor, stream=None) -> dict:
         """Time the near-field source groups and the P2M/L2P leaves per wave

@@ -12,6 +12,8 @@ STATUS_NAMES = {0: "FMM_OK", 1: "FMM_EINVAL", 2: "FMM_ENOMEM", 3: "FMM_EDEVICE",
                 4: "FMM_ENOTSUP", 5: "FMM_ESTATE"}
 FMM_FP64, FMM_FP32 = 0, 1
 FMM_MIN_ORDER, FMM_MAX_ORDER = 1, 10
+FMM_PLAN_NO_WORKSPACE = 1
+FMM_NOALLOC_MAX_BYTES = 128 << 20
 FMM_TIE_SOURCE, FMM_TIE_TARGET = 0, 1
 FMM_LISTS_CROSS_LEVEL, FMM_LISTS_SAME_LEVEL = 0, 1
 FMM_NSTAGES = 7
@@ -70,6 +72,7 @@ def lib() -> ctypes.CDLL:
                                                ctypes.POINTER(FmmAllocator), ctypes.c_uint, vp,
                                                ctypes.POINTER(vp)]
         L.fmm_plan_workspace_bytes.argtypes = [i64, ctypes.POINTER(FmmParams), i64p]
+        L.fmm_evaluate_noalloc.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
         L.fmm_plan_create_st.argtypes = [vp, i64, vp, i64, ctypes.POINTER(FmmParams),
                                          ctypes.POINTER(FmmAllocator), ctypes.c_uint, vp,
                                          ctypes.POINTER(vp)]
@@ -97,7 +100,7 @@ def lib() -> ctypes.CDLL:
                   "fmm_evaluate_transposed", "fmm_adjoint", "fmm_multi_plan_create",
                   "fmm_graph_create", "fmm_graph_launch", "fmm_graph_destroy",
                   "fmm_plan_autotune", "fmm_plan_create_ex", "fmm_multi_plan_create_ex",
-                  "fmm_plan_workspace_bytes", "fmm_plan_create_st"):
+                  "fmm_plan_workspace_bytes", "fmm_plan_create_st", "fmm_evaluate_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib

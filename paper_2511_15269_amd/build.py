@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libfmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "tables.cpp", "sort.hip", "tree.hip", "lists.hip", "direct.hip", "eval.hip", "batch.hip",
-           "multi.hip"]
+           "multi.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(os.path.dirname(PKG), "include")]

@@ -265,33 +265,13 @@ void check_params(const fmm_params* prm, int64_t n) {
 void check_allocator(const fmm_allocator* a, unsigned flags) {
   if (a && (!a->alloc || !a->free))
     throw Error{FMM_EINVAL, "allocator needs both an alloc and a free callback"};
-  if (flags != 0u) throw Error{FMM_EINVAL, "unknown plan flags"};
+  if ((flags & ~FMM_PLAN_NO_WORKSPACE) != 0u) throw Error{FMM_EINVAL, "unknown plan flags"};
 }
 
-void use_allocator(fmm_plan* pl, const fmm_allocator* a, hipStream_t st) {
+void use_allocator(fmm_plan* pl, const fmm_allocator* a, hipStream_t st, unsigned flags = 0u) {
   if (a) pl->allocator = *a;
   pl->alloc_stream = st;
-}
-
-template <typename F>
-fmm_status guard(F&& f) {
-  try {
-    clear_error();
-    f();
-    return FMM_OK;
-  } catch (const Error& e) {
-    set_error(e.msg);
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return FMM_ENOMEM;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return FMM_EDEVICE;
-  } catch (...) {
-    set_error("unknown error");
-    return FMM_EDEVICE;
-  }
+  pl->flags = flags;
 }
 
 void check_workspace(const fmm_plan* pl) {
@@ -368,8 +348,10 @@ void alloc_workspace(fmm_plan* pl, hipStream_t st) {
   const fmm_params* prm = &pl->prm;
   const bool bat = batched_plan(pl);
   const WorkspaceLayout L = workspace_layout(pl->n, pl->nbox, *prm, bat);
-  pl->workspace_bytes = L.total;
-  bind_workspace(pl->ws, (char*)plan_alloc(pl, L.total), L, 10);
+  if (!(pl->flags & FMM_PLAN_NO_WORKSPACE)) {
+    pl->workspace_bytes = L.total;
+    bind_workspace(pl->ws, (char*)plan_alloc(pl, L.total), L, 10);
+  }
   if (bat) {
     const size_t K = (size_t)ncoef(prm->p);
     const size_t ni =
@@ -401,7 +383,7 @@ fmm_status fmm_plan_create_ex(const double* pos, int64_t n, const fmm_params* pr
     check_allocator(allocator, flags);
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
-    use_allocator(pl.get(), allocator, st);
+    use_allocator(pl.get(), allocator, st, flags);
     try {
       build_structure(pl.get(), pos, n, prm, st);
       make_steps(pl.get(), {{TreeDesc{pl->L, pl->level_off, 0, 0}}}, st);
@@ -436,7 +418,7 @@ fmm_status fmm_multi_plan_create_ex(const double* pos, const int64_t* offsets, i
     hipStream_t st = (hipStream_t)stream;
     std::vector<std::unique_ptr<fmm_plan>> subs;
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
-    use_allocator(pl.get(), allocator, st);
+    use_allocator(pl.get(), allocator, st, flags);
     auto free_subs = [&] {
       for (auto& u : subs) plan_free_all(u.get());
       subs.clear();
@@ -492,7 +474,7 @@ fmm_status fmm_plan_create_st(const double* src, int64_t ns, const double* tgt, 
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<fmm_plan> sub[2];
     std::unique_ptr<fmm_plan> pl(new fmm_plan());
-    use_allocator(pl.get(), allocator, st);
+    use_allocator(pl.get(), allocator, st, flags);
     auto free_subs = [&] {
       for (auto& u : sub)
         if (u) plan_free_all(u.get());
@@ -568,6 +550,7 @@ fmm_status fmm_evaluate(fmm_plan* pl, const void* q, int nrhs, void* pot,
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
+    check_workspace(pl);
     run_vectors(pl, 0, q, nrhs, pot, field, (hipStream_t)stream);
   });
 }
@@ -579,6 +562,7 @@ fmm_status fmm_evaluate_transposed(fmm_plan* pl, const void* q, int nrhs, void* 
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
+    check_workspace(pl);
     run_vectors(pl, 1, q, nrhs, pot, field, (hipStream_t)stream);
   });
 }
@@ -722,6 +706,7 @@ fmm_status fmm_graph_create(fmm_plan* pl, int transposed, const void* q, int nrh
     if (!q || !pot) throw Error{FMM_EINVAL, "q and pot must not be NULL"};
     if (nrhs < 1 || nrhs > pl->prm.max_rhs) throw Error{FMM_EINVAL, "nrhs out of range"};
     check_device(pl);
+    check_workspace(pl);
     std::unique_ptr<fmm_graph> g(new fmm_graph());
     g->device = pl->device;
     hipStream_t cs = nullptr;
@@ -784,6 +769,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
   return guard([&] {
     if (!pl || !q) throw Error{FMM_EINVAL, "plan and q must not be NULL"};
     check_device(pl);
+    check_workspace(pl);
     const hipStream_t st = (hipStream_t)stream;
     const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
     void* pot = nullptr;

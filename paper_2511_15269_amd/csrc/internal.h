@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -89,6 +91,7 @@ struct Workspace {
   void* bD = nullptr;    // [nbox][K][32]
   void* bpot = nullptr;  // [n][32]
   void* bfld = nullptr;  // [n][3][32]
+  bool stages = true;    // record stage-timing events when the plan profiles
 };
 
 // Byte offsets of the workspace buffers inside one allocation, each
@@ -169,6 +172,7 @@ struct fmm_plan {
   // FMM_PLAN_NO_WORKSPACE
   fmm::Workspace ws;
   size_t workspace_bytes = 0;
+  unsigned flags = 0;  // fmm_plan_create_ex flags
   // batched M2L partial rows [n_items][K][32] (FP32 plans with max_rhs > 1);
   // sized by the lists, so held with them
   void* bpart = nullptr;
@@ -292,8 +296,8 @@ enum { kStSort = 0, kStP2M, kStM2M, kStM2L, kStL2L, kStL2P, kStP2P };
 // pair recorded on the stream the stage runs on.
 struct StageMarks {
   std::vector<hipEvent_t>* row = nullptr;
-  explicit StageMarks(fmm_plan* pl) {
-    if (!pl->profiling) return;
+  explicit StageMarks(fmm_plan* pl, bool enabled = true) {
+    if (!pl->profiling || !enabled) return;
     pl->ev_rows.emplace_back();
     row = &pl->ev_rows.back();
     for (int k = 0; k < 2 * FMM_NSTAGES; ++k) row->push_back(take_event(pl));
@@ -305,6 +309,29 @@ struct StageMarks {
     if (row) FMM_HIP(hipEventRecord((*row)[2 * k + 1], s));
   }
 };
+
+// Runs f, turning exceptions into a status and the thread's error message
+// (every C entry point).
+template <typename F>
+fmm_status guard(F&& f) {
+  try {
+    clear_error();
+    f();
+    return FMM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FMM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return FMM_EDEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return FMM_EDEVICE;
+  }
+}
 
 // Sorting primitives (sort.hip).
 size_t sort_pairs_u64_i32_temp(int n);

@@ -102,6 +102,8 @@ typedef struct {
   int64_t device_bytes; /* device memory held by the plan (all of it)      */
   int64_t workspace_bytes; /* of which the evaluation workspace (see
                               fmm_plan_workspace_bytes)                    */
+  int64_t p2p_items;    /* near-field work items (direct lists longer than
+                           about 2^16 interactions are split into several) */
 } fmm_plan_info;
 
 /* Source of the plan's device memory (fmm_plan_create_ex).  alloc returns

@@ -33,7 +33,8 @@ class FmmPlanInfo(ctypes.Structure):
                 ("splits", ctypes.c_int32), ("nbox", ctypes.c_int64),
                 ("nleaf", ctypes.c_int64), ("n_m2l", ctypes.c_int64),
                 ("n_p2p", ctypes.c_int64), ("p2p_interactions", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("p2p_items", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -539,6 +539,7 @@ fmm_status fmm_plan_get_info(const fmm_plan* pl, fmm_plan_info* info) {
     r.p2p_interactions = pl->p2p_inter;
     r.device_bytes = (int64_t)pl->device_bytes;
     r.workspace_bytes = (int64_t)pl->workspace_bytes;
+    r.p2p_items = pl->lists[0].n_pitems;
     *info = r;
   });
 }

@@ -342,9 +342,11 @@ constexpr int kChunk = 8;
 // P2P: writes -1/(4 pi) sum q/r and the matching field over the direct list,
 // in leaf order (near[i] and near[n + 3 i + c]); L2P adds the far field and
 // writes the outputs in input order.
-// Block = target leaf leaf0 + blockIdx.x, lane = target point (position from
-// the plan's leaf-ordered coordinates; the sources' records are this
-// pass's, written by P2M).  G source groups: lanes
+// Block = one near-field work item (a run of a target leaf's direct list;
+// most leaves have one), lane = target point (position from the plan's
+// leaf-ordered coordinates; the sources' records are this pass's, written
+// by P2M).  A leaf's only item writes its near field; the items of a split
+// leaf write partial rows that k_p2p_sum adds in item order.  G source groups: lanes
 // [g*64/G, (g+1)*64/G) share targets with the other groups but walk every
 // G-th source point starting at point g.  G = 1 keeps all source reads
 // wave-uniform (scalar loads).  G = 2, 4 fill the wave when leaves hold at
@@ -356,19 +358,23 @@ constexpr int kChunk = 8;
 // combined with cross-lane shuffles in a fixed order.
 template <typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_p2p(
-    int64_t n, int64_t leaf0, const int32_t* __restrict__ leaf_start,
-    const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ zs,
-    const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_ptr,
-    const int32_t* __restrict__ p2p_src, int dup, T* __restrict__ near) {
+    int64_t n, const int32_t* __restrict__ item_leaf, const int32_t* __restrict__ item_kb,
+    const int32_t* __restrict__ item_ke, const int64_t* __restrict__ item_out,
+    const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const Src<T>* __restrict__ src, const int32_t* __restrict__ p2p_src, int dup,
+    T* __restrict__ near, T* __restrict__ part) {
   constexpr int TL = 64 / G;  // targets per pass
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   // G > 1: one source leaf (at most TL points) staged as 16-byte words
   __shared__ __align__(32) double2 stage[G > 1 ? 2 * TL : 1];
-  const int leaf = (int)(leaf0 + blockIdx.x);
+  const int item = blockIdx.x;
+  const int leaf = item_leaf[item];
   const int lane = threadIdx.x;
   const int g = G == 1 ? 0 : lane / TL;
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
-  const int pb = p2p_ptr[leaf], pe = p2p_ptr[leaf + 1];
+  const int pb = item_kb[item], pe = item_ke[item];
+  const int64_t po = item_out[item];
   for (int i0 = st; i0 < en; i0 += TL) {
     const int i = i0 + lane % TL;
     const bool live = i < en;
@@ -445,14 +451,58 @@ __global__ __launch_bounds__(64) void k_p2p(
       }
     }
     if (live && g == 0) {
-      near[i] = -T(kInv4Pi) * u;
-      if (FIELD) {
-        // field = -grad u;  grad of the near part is +(1/4pi) sum q d/r^3
-        T* f = near + n + 3 * (int64_t)i;
-        f[0] = -T(kInv4Pi) * gx;
-        f[1] = -T(kInv4Pi) * gy;
-        f[2] = -T(kInv4Pi) * gz;
+      // field = -grad u;  grad of the near part is +(1/4pi) sum q d/r^3
+      if (po < 0) {  // the leaf's only item: its near field
+        near[i] = -T(kInv4Pi) * u;
+        if (FIELD) {
+          T* f = near + n + 3 * (int64_t)i;
+          f[0] = -T(kInv4Pi) * gx;
+          f[1] = -T(kInv4Pi) * gy;
+          f[2] = -T(kInv4Pi) * gz;
+        }
+      } else {  // one of several items of the leaf: rows of its partial sums
+        const int nt = en - st, li = i - st;
+        T* r = part + po;
+        r[li] = -T(kInv4Pi) * u;
+        if (FIELD) {
+          r[nt + li] = -T(kInv4Pi) * gx;
+          r[2 * nt + li] = -T(kInv4Pi) * gy;
+          r[3 * nt + li] = -T(kInv4Pi) * gz;
+        }
       }
+    }
+  }
+}
+
+// Near field of the leaves whose direct list was split into several items:
+// the items' partial rows added in item order (Neumaier-compensated in
+// FP32).  Block = split leaf, thread = target point.
+template <typename T, bool FIELD>
+__global__ __launch_bounds__(64) void k_p2p_sum(
+    int64_t n, const int32_t* __restrict__ split_leaf, const int32_t* __restrict__ split_first,
+    const int32_t* __restrict__ split_cnt, const int64_t* __restrict__ item_out,
+    const int32_t* __restrict__ leaf_start, const T* __restrict__ part, T* __restrict__ near) {
+  constexpr bool kComp = sizeof(T) == 4;
+  const int leaf = split_leaf[blockIdx.x];
+  const int f = split_first[blockIdx.x], c = split_cnt[blockIdx.x];
+  const int st = leaf_start[leaf], nt = leaf_start[leaf + 1] - st;
+  for (int li = threadIdx.x; li < nt; li += blockDim.x) {
+#pragma unroll
+    for (int comp = 0; comp < (FIELD ? 4 : 1); ++comp) {
+      T acc = T(0), cc = T(0);
+      for (int j = f; j < f + c; ++j) {
+        const T x = part[item_out[j] + (int64_t)comp * nt + li];
+        if (kComp)
+          neumaier(acc, cc, x);
+        else
+          acc += x;
+      }
+      acc += cc;
+      const int64_t i = st + li;
+      if (comp == 0)
+        near[i] = acc;
+      else
+        near[n + 3 * i + comp - 1] = acc;
     }
   }
 }
@@ -534,8 +584,10 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   mk.begin(kStP2P, st);
   const int G = p2p_groups(pl);
   auto p2p = [&](auto kern) {
-    kern<<<(unsigned)nlt, 64, 0, st>>>(n, TS.leaf0, pl->leaf_start, pl->xs, pl->ys, pl->zs, src,
-                                       Ls.p2p_ptr, Ls.p2p_src, pl->has_dup ? 1 : 0, near);
+    kern<<<(unsigned)Ls.n_pitems, 64, 0, st>>>(n, Ls.pitem_leaf, Ls.pitem_kb, Ls.pitem_ke,
+                                               Ls.pitem_out, pl->leaf_start, pl->xs, pl->ys,
+                                               pl->zs, src, Ls.p2p_src, pl->has_dup ? 1 : 0, near,
+                                               (T*)Ls.p2p_part);
   };
   if (field) {
     if (G == 1) p2p(k_p2p<T, true, 1>);
@@ -545,6 +597,15 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
     if (G == 1) p2p(k_p2p<T, false, 1>);
     else if (G == 2) p2p(k_p2p<T, false, 2>);
     else p2p(k_p2p<T, false, 4>);
+  }
+  if (Ls.n_psplit > 0) {
+    auto sum = [&](auto kern) {
+      kern<<<(unsigned)Ls.n_psplit, 64, 0, st>>>(n, Ls.psplit_leaf, Ls.psplit_first,
+                                                 Ls.psplit_cnt, Ls.pitem_out, pl->leaf_start,
+                                                 (const T*)Ls.p2p_part, near);
+    };
+    if (field) sum(k_p2p_sum<T, true>);
+    else sum(k_p2p_sum<T, false>);
   }
   mk.end(kStP2P, st);
   mk.begin(kStL2P, st);

@@ -74,7 +74,28 @@ struct ListSet {
   int32_t* seg_lanes = nullptr;
   int32_t* zero_box = nullptr;
   int64_t n_m2l = 0, n_p2p = 0, n_items = 0, n_blocks = 0, n_zero = 0;
+  // Near-field work items: item j covers direct pairs [pitem_kb[j],
+  // pitem_ke[j]) of target leaf pitem_leaf[j], about kP2PItemWork
+  // interactions or one whole leaf; every target leaf has at least one.
+  // pitem_out[j] < 0: the leaf's only item, written to the near field;
+  // otherwise the element offset of the item's partial sums (4 rows of the
+  // leaf's point count: potential, field x, y, z) in p2p_part.  The split
+  // leaves psplit_leaf[i] add the partials of their psplit_cnt[i] items
+  // from psplit_first[i] on, in item order.
+  int32_t* pitem_leaf = nullptr;
+  int32_t* pitem_kb = nullptr;
+  int32_t* pitem_ke = nullptr;
+  int64_t* pitem_out = nullptr;
+  int32_t* psplit_leaf = nullptr;
+  int32_t* psplit_first = nullptr;
+  int32_t* psplit_cnt = nullptr;
+  void* p2p_part = nullptr;
+  int64_t n_pitems = 0, n_psplit = 0, p2p_part_elems = 0;
 };
+
+// Interactions per near-field work item before a leaf's direct list is
+// split (2^16: the uniform 2^20 cube keeps one item per leaf).
+constexpr int64_t kP2PItemWork = 1 << 16;
 
 // Per-evaluation device buffers (all but the M2L partial rows of the
 // batched form): leaf-ordered source records, expansions, the near field,
@@ -261,8 +282,10 @@ void build_tree(fmm_plan* pl, const double* pos, hipStream_t st);
 // between the source tree src and the target tree tgt of the plan (the
 // same tree for a plan over one point set).
 void build_lists(fmm_plan* pl, const TreeDesc& src, const TreeDesc& tgt, hipStream_t st);
-// M2L work items and block segments of one list set from its CSR (lists.hip).
+// M2L work items and block segments of one list set from its CSR, and the
+// near-field work items of direction dir (lists.hip).
 void make_items(fmm_plan* pl, ListSet& S, hipStream_t st);
+void make_p2p_items(fmm_plan* pl, int dir, hipStream_t st);
 // Operator tables for order p (tables.cpp), cached per process/device.
 const void* get_tables(int p, int precision, int device);
 // Evaluation (eval.hip): dir 0 = G-hat, dir 1 = G-hat^T.

@@ -215,6 +215,82 @@ void make_items(fmm_plan* pl, ListSet& S, hipStream_t st) {
   FMM_HIP(hipStreamSynchronize(st));
 }
 
+// Near-field work items of direction dir over the target side's leaves:
+// a leaf's direct list is cut into runs of source leaves of about
+// kP2PItemWork interactions (a run ends before the source leaf that would
+// pass the budget; a run holds at least one leaf), so that leaves with very
+// long lists (clustered points) spread over many blocks.
+void make_p2p_items(fmm_plan* pl, int dir, hipStream_t st) {
+  ListSet& S = pl->lists[dir];
+  const Side& T = tgt_side(pl, dir);
+  std::vector<int32_t> ptr(pl->nleaf + 1), src(std::max<int64_t>(S.n_p2p, 1)), ls(pl->nleaf + 1);
+  FMM_HIP(hipMemcpyAsync(ptr.data(), S.p2p_ptr, sizeof(int32_t) * (pl->nleaf + 1),
+                         hipMemcpyDeviceToHost, st));
+  if (S.n_p2p > 0)
+    FMM_HIP(hipMemcpyAsync(src.data(), S.p2p_src, sizeof(int32_t) * S.n_p2p,
+                           hipMemcpyDeviceToHost, st));
+  FMM_HIP(hipMemcpyAsync(ls.data(), pl->leaf_start, sizeof(int32_t) * (pl->nleaf + 1),
+                         hipMemcpyDeviceToHost, st));
+  FMM_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> il, kb, ke, sl, sf, sc;
+  std::vector<int64_t> out;
+  int64_t part = 0;
+  for (int64_t t = T.leaf0; t < T.leaf0 + T.nleaf; ++t) {
+    const int64_t nt = ls[t + 1] - ls[t];
+    const size_t first = il.size();
+    int32_t b = ptr[t];
+    int64_t acc = 0;
+    for (int32_t k = ptr[t]; k < ptr[t + 1]; ++k) {
+      const int64_t w = nt * (int64_t)(ls[src[k] + 1] - ls[src[k]]);
+      if (k > b && acc + w > kP2PItemWork) {
+        il.push_back((int32_t)t);
+        kb.push_back(b);
+        ke.push_back(k);
+        b = k;
+        acc = 0;
+      }
+      acc += w;
+    }
+    il.push_back((int32_t)t);
+    kb.push_back(b);
+    ke.push_back(ptr[t + 1]);
+    const size_t cnt = il.size() - first;
+    if (cnt == 1) {
+      out.push_back(-1);
+      continue;
+    }
+    for (size_t j = 0; j < cnt; ++j) {
+      out.push_back(part);
+      part += 4 * nt;
+    }
+    sl.push_back((int32_t)t);
+    sf.push_back((int32_t)first);
+    sc.push_back((int32_t)cnt);
+  }
+  auto up32 = [&](const std::vector<int32_t>& v) {
+    int32_t* d = (int32_t*)plan_alloc(pl, sizeof(int32_t) * std::max<size_t>(v.size(), 1));
+    if (!v.empty())
+      FMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, st));
+    return d;
+  };
+  S.n_pitems = (int64_t)il.size();
+  S.n_psplit = (int64_t)sl.size();
+  S.pitem_leaf = up32(il);
+  S.pitem_kb = up32(kb);
+  S.pitem_ke = up32(ke);
+  S.psplit_leaf = up32(sl);
+  S.psplit_first = up32(sf);
+  S.psplit_cnt = up32(sc);
+  S.pitem_out = (int64_t*)plan_alloc(pl, sizeof(int64_t) * std::max<size_t>(out.size(), 1));
+  if (!out.empty())
+    FMM_HIP(hipMemcpyAsync(S.pitem_out, out.data(), sizeof(int64_t) * out.size(),
+                           hipMemcpyHostToDevice, st));
+  S.p2p_part_elems = part;
+  const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
+  S.p2p_part = part > 0 ? plan_alloc(pl, es * (size_t)part) : nullptr;
+  FMM_HIP(hipStreamSynchronize(st));
+}
+
 void build_lists(fmm_plan* pl, const TreeDesc& ts, const TreeDesc& tt, hipStream_t st) {
   const int Ls = ts.L, Lt = tt.L, nch = pl->nch;
   const int T = 256;
@@ -391,6 +467,8 @@ void build_lists(fmm_plan* pl, const TreeDesc& ts, const TreeDesc& tt, hipStream
   pl->p2p_inter = inter;
   make_items(pl, F, st);
   make_items(pl, A, st);
+  make_p2p_items(pl, 0, st);
+  make_p2p_items(pl, 1, st);
 }
 
 }  // namespace fmm

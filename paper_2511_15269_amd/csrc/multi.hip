@@ -122,10 +122,14 @@ void build_union(fmm_plan* U, const std::vector<const fmm_plan*>& subs, hipStrea
   }
   FMM_HIP(hipStreamSynchronize(st));
   if (!lists) return;
-  // M2L work items over the union's lists: blocks may then mix targets of
-  // different problems
+  // M2L and near-field work items over the union's lists: blocks may then
+  // mix targets of different problems
+  U->side[0].npt = U->n;
+  U->side[0].nleaf = U->nleaf;
   make_items(U, U->lists[0], st);
   make_items(U, U->lists[1], st);
+  make_p2p_items(U, 0, st);
+  make_p2p_items(U, 1, st);
 }
 
 }  // namespace fmm

@@ -511,3 +511,28 @@ def test_autotuned_tiles_give_the_same_results(fmm, prec, n, leaf, s, tol):
     ub, fb = b.evaluate(qt)
     assert _rel(ub.double().cpu().numpy(), ua.double().cpu().numpy()) <= tol
     assert _rel(fb.double().cpu().numpy(), fa.double().cpu().numpy()) <= tol
+
+
+@pytest.mark.parametrize("prec,n,p,leaf,s,theta", [("fp64", 30000, 5, 64, 2, 0.6),
+                                                   ("fp32", 25000, 6, 32, 2, 0.7)])
+def test_split_near_field_lists_match_oracle(fmm, prec, n, p, leaf, s, theta):
+    """Clustered points give some leaves direct lists far longer than the
+    near-field work-item budget: those lists are cut into several items whose
+    partial sums are added afterwards; the result must still match the
+    oracle, which sums every list in one go."""
+    from oracle.fmm import fmm as oracle_fmm
+    _say(f"[split near field] clustered n={n} p={p} leaf={leaf} s={s} theta={theta} {prec}")
+    pos, q = workloads.clustered(n, 5)
+    u0, f0 = oracle_fmm(pos, q, p, leaf, s, theta)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=p, leaf_max=leaf, splits=s, theta=theta,
+                    precision=prec)
+    inf = plan.info()
+    assert inf["p2p_items"] > inf["nleaf"], "no leaf was split: the case does not test splitting"
+    Q = torch.from_numpy(q).to(dt).cuda()
+    u, f = plan.evaluate(Q)
+    v, _ = plan.evaluate(Q, field=False)
+    torch.cuda.synchronize()
+    bound = 1e-10 if prec == "fp64" else 1e-5
+    assert _rel(u.cpu().numpy(), u0) <= bound and _rel(f.cpu().numpy(), f0) <= bound
+    assert torch.equal(u, v)

@@ -160,6 +160,8 @@ def main():
                     help="skip the multi-vector and uneven-problem-set variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter scale)")
+    ap.add_argument("--counters-batched", action="store_true",
+                    help="with --counters: the 32-vector FP32 pass on 2^18 points instead")
     ap.add_argument("--counters", action="store_true",
                     help="only the headline pass (plan, autotune, warm-up, timed steps) and, with "
                          "--copy-calibration, the calibration copy: the program to run under "
@@ -491,16 +493,29 @@ def counters_run(args, pos, q):
 
     import paper_2511_15269_amd as F
     dev = torch.device("cuda:0")
-    pos_d = torch.from_numpy(pos).to(dev)
-    dt = torch.float64 if args.precision == "fp64" else torch.float32
-    qd = torch.from_numpy(q).to(dev).to(dt)
-    plan = F.Plan(pos_d, p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
-                  precision=args.precision)
-    tiles = plan.autotune(qd)
-    pot = torch.empty((1, args.n), dtype=dt, device=dev)
-    fld = torch.empty((1, args.n, 3), dtype=dt, device=dev)
-    for _ in range(args.warmup + args.steps):
-        plan.evaluate(qd.reshape(1, -1), out=(pot, fld))
+    if args.counters_batched:
+        import workloads
+        n, R = 1 << 18, 32
+        pos, Q = workloads.uniform_cube(n, 0, nrhs=R)
+        plan = F.Plan(torch.from_numpy(pos).to(dev), p=args.p, leaf_max=args.leaf,
+                      splits=args.splits, theta=args.theta, precision="fp32", max_rhs=R)
+        Qd = torch.from_numpy(Q).to(dev).float()
+        tiles = None
+        pot = torch.empty((R, n), dtype=torch.float32, device=dev)
+        fld = torch.empty((R, n, 3), dtype=torch.float32, device=dev)
+        for _ in range(args.warmup + args.steps):
+            plan.evaluate(Qd, out=(pot, fld))
+    else:
+        pos_d = torch.from_numpy(pos).to(dev)
+        dt = torch.float64 if args.precision == "fp64" else torch.float32
+        qd = torch.from_numpy(q).to(dev).to(dt)
+        plan = F.Plan(pos_d, p=args.p, leaf_max=args.leaf, splits=args.splits, theta=args.theta,
+                      precision=args.precision)
+        tiles = plan.autotune(qd)
+        pot = torch.empty((1, args.n), dtype=dt, device=dev)
+        fld = torch.empty((1, args.n, 3), dtype=dt, device=dev)
+        for _ in range(args.warmup + args.steps):
+            plan.evaluate(qd.reshape(1, -1), out=(pot, fld))
     torch.cuda.synchronize()
     if args.copy_calibration:
         a = torch.empty(1 << 25, dtype=torch.float64, device=dev)

@@ -368,7 +368,11 @@ __global__ __launch_bounds__(64) void k_p2p(
   constexpr bool kComp = sizeof(T) == 4;  // FP32: compensated sums
   // G > 1: one source leaf (at most TL points) staged as 16-byte words
   __shared__ __align__(32) double2 stage[G > 1 ? 2 * TL : 1];
-  const int item = blockIdx.x;
+  // items in target-leaf order, handed to the XCDs in runs of 64:
+  // neighbouring target leaves share most source leaves, so their records
+  // stay in one XCD's L2, while leaves of unequal cost (several problems,
+  // clustered points) spread over all XCDs
+  const int item = (int)xcd_chunked<64>(blockIdx.x, gridDim.x);
   const int leaf = item_leaf[item];
   const int lane = threadIdx.x;
   const int g = G == 1 ? 0 : lane / TL;

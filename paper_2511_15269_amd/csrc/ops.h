@@ -498,6 +498,21 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// The same for blocks of unequal cost: logical blocks go to the XCDs in
+// chunks of K consecutive ones, chunk c to XCD c % 8, so that neighbours
+// still share an L2 while runs of expensive blocks spread over all XCDs;
+// the tail that does not fill a round of 8 chunks is placed as xcd_block
+// places it.  A bijection of [0, nb).
+template <unsigned K>
+__device__ __forceinline__ unsigned xcd_chunked(unsigned b, unsigned nb) {
+  constexpr unsigned kXcd = 8;
+  const unsigned full = nb / (kXcd * K);  // complete rounds
+  const unsigned x = b % kXcd, j = b / kXcd;
+  if (j < full * K) return ((j / K) * kXcd + x) * K + j % K;
+  const unsigned base = full * kXcd * K;
+  return base + xcd_block(b - base, nb - base);
+}
+
 // ------------------------------------------------------ lane reductions
 // Cross-lane moves through the VALU's data-parallel primitives (no LDS).
 // CTRL: quad_perm / row_mirror / row_bcast selector; RM: rows written (the

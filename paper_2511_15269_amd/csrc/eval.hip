@@ -48,10 +48,34 @@ using namespace ops;
 
 // ---------------------------------------------------------------- P2M
 // C_leaf = normc * sum_i q_i R-hat((x_i - c) / rho)  (scaled multipole).
-// G leaves per wave (LW = 64/G lanes each, lane = point); the per-lane sums
-// are combined by a butterfly over the leaf's lanes.  The kernel also does
-// the sort stage: it reads each charge in input order and writes the leaf's
+// G leaves per wave (LW = 64/G lanes each, lane = point).  The per-lane
+// terms go to LDS in chunks of kP2MRows coefficients (row r of lane l at
+// r * kRow + l); each chunk is then summed over every leaf's lanes by one
+// lane per (leaf, coefficient), in a fixed order (two interleaved partial
+// sums).  The kernel also does the
+// sort stage: it reads each charge in input order and writes the leaf's
 // 32-byte source records that P2P reads.
+constexpr int kRow = 65;       // LDS row stride: a lane's rows fall in different banks
+constexpr int kP2MRows = 16;   // coefficients per chunk
+
+// Row r of buf holds coefficient rowk[r] (or k0 + r when rowk is NULL) of
+// every lane; cs[leaf][coefficient] = the sum over the leaf's LW lanes.
+template <int LW, int K, typename T>
+__device__ __forceinline__ void leaf_sums(const T* buf, const int* rowk, int nr, int k0,
+                                          T (*cs)[K], int G) {
+  for (int t = threadIdx.x; t < G * nr; t += 64) {
+    const int hh = t / nr, r = t - hh * nr;
+    const T* row = buf + r * kRow + hh * LW;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int l = 0; l < LW; l += 2) {
+      s0 += row[l];
+      s1 += row[l + 1];
+    }
+    cs[hh][rowk ? rowk[r] : k0 + r] = s0 + s1;
+  }
+}
+
 template <int P, typename T, int G>
 __global__ __launch_bounds__(64) void k_p2m(
     int64_t nleaf, const int32_t* __restrict__ leaf_box,
@@ -64,6 +88,8 @@ __global__ __launch_bounds__(64) void k_p2m(
   constexpr int K = K_<P>::value;
   constexpr int LW = 64 / G;
   __shared__ T cs[G][K];  // finished sums, stored coalesced at the end
+  __shared__ T buf[(kP2MRows - 1) * kRow + 64];
+  __shared__ int rowk[kP2MRows];  // coefficient held by each row
   const int lane = threadIdx.x;
   const int h = lane / LW, l = lane % LW;
   const int64_t leaf = (int64_t)blockIdx.x * G + h;
@@ -72,16 +98,25 @@ __global__ __launch_bounds__(64) void k_p2m(
   const int st = has ? leaf_start[leaf] : 0, en = has ? leaf_start[leaf + 1] : 0;
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
   if (G > 1) {
-    // at most one point per lane: reduce every coefficient as it is formed
+    // at most one point per lane: every term goes to LDS as it is formed
+    // (the basis comes order by order, so rows record their coefficient)
     const int j = st + l;
     const bool pt = j < en;
     const int jj = pt ? j : st;
     const T qj = pt ? q[perm[j]] : T(0);
     if (pt) src[j] = Src<T>{xs[j], ys[j], zs[j], qj};
+    int e = 0;  // terms emitted so far (the same in every lane)
     regular_basis<P, T>(T((xs[jj] - ox) * ir), T((ys[jj] - oy) * ir), T((zs[jj] - oz) * ir),
                         [&](int k, T v) {
-                          const T sum = group_sum<LW>(qj * v);
-                          if (l == LW - 1) cs[h][k] = sum;
+                          const int r = e % kP2MRows;
+                          buf[r * kRow + lane] = qj * v;
+                          if (lane == 0) rowk[r] = k;
+                          ++e;
+                          if (r == kP2MRows - 1 || e == K) {
+                            __syncthreads();
+                            leaf_sums<LW, K, T>(buf, rowk, r + 1, 0, cs, G);
+                            __syncthreads();
+                          }
                         });
   } else {
     T acc[K];
@@ -94,12 +129,15 @@ __global__ __launch_bounds__(64) void k_p2m(
                           [&](int k, T v) { acc[k] = fma(qj, v, acc[k]); });
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const T sum = group_sum<LW>(acc[k]);
-      if (l == LW - 1) cs[0][k] = sum;
+    for (int k0 = 0; k0 < K; k0 += kP2MRows) {
+#pragma unroll
+      for (int r = 0; r < kP2MRows; ++r)
+        if (k0 + r < K) buf[r * kRow + lane] = acc[k0 + r];
+      __syncthreads();
+      leaf_sums<LW, K, T>(buf, nullptr, (K - k0 < kP2MRows ? K - k0 : kP2MRows), k0, cs, 1);
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int idx = lane; idx < G * K; idx += 64) {
     const int hh = idx / K, k = idx - hh * K;
     const int64_t lf = (int64_t)blockIdx.x * G + hh;
@@ -137,12 +175,9 @@ __global__ __launch_bounds__(64) void k_m2m(
 }
 
 // ---------------------------------------------------------------- M2L
-// Lane-private LDS rows, row stride kRow elements: row r of lane l at
-// r * kRow + l.  The stride of 65 puts the rows of one lane in different
-// banks, so that the segment sums below (lanes reading different rows of
-// the same lane) do not collide, while a wave's access to one row stays
-// contiguous.
-constexpr int kRow = 65;
+// Lane-private LDS rows as in P2M (row r of lane l at r * kRow + l): the
+// segment sums below read different rows of the same lane without bank
+// conflicts, while a wave's access to one row stays contiguous.
 
 // For every target segment of this block (seg_tgt[g], lanes
 // [seg_lanes[g] & 255, seg_lanes[g] >> 8), g in [sb, se)), adds rows

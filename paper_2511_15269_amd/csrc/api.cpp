@@ -214,19 +214,67 @@ void make_steps(fmm_plan* pl, const std::vector<std::vector<TreeDesc>>& groups,
     S.l2l_sum.a = upload(all);
     S.l2l_sum.b = nullptr;
   }
-  // boxes whose local is formed but which receive no M2L pair in a direction:
-  // their M2L sum is zero and is written by a fill before the level chain
+  // Final locals of each direction's target side.  Re-centring a truncated
+  // local expansion is exact, so a box's final local is its own M2L sum plus
+  // the translated M2L sums of all its ancestors; the parents of the leaves
+  // get theirs that way in one launch (every translation independent), the
+  // leaves then add one translation of their parent's final local.
   for (int d = 0; d < 2; ++d) {
     ListSet& L = pl->lists[d];
-    const std::vector<int32_t>& all = all_of[pl->nsides == 1 ? 0 : 1 - d];
-    std::vector<int32_t> ptr(pl->nbox + 1), z;
+    const std::vector<TreeDesc>& trees = groups[pl->nsides == 1 ? 0 : 1 - d];
+    std::vector<int32_t> ptr(pl->nbox + 1);
     FMM_HIP(hipMemcpyAsync(ptr.data(), L.m2l_ptr, sizeof(int32_t) * (pl->nbox + 1),
                            hipMemcpyDeviceToHost, st));
     FMM_HIP(hipStreamSynchronize(st));
-    for (int32_t b : all)
-      if (ptr[b + 1] == ptr[b]) z.push_back(b);
-    L.n_zero = (int64_t)z.size();
-    L.zero_box = upload(z);
+    auto has = [&](int64_t b) { return ptr[b + 1] > ptr[b]; };
+    std::vector<int32_t> box[2], own[2];
+    std::vector<std::vector<int32_t>> src[2];
+    for (const TreeDesc& t : trees) {
+      std::vector<char> formed;  // parents of the leaves with a final local
+      if (t.L >= 1) {
+        const int lp = t.L - 1;
+        const int64_t np = t.level_off[lp + 1] - t.level_off[lp];
+        formed.assign(np, 0);
+        for (int64_t i = 0; i < np; ++i) {
+          const int64_t b = t.box_base + t.level_off[lp] + i;
+          std::vector<int32_t> anc;
+          for (int l = lp - 1; l >= 0; --l) {
+            const int64_t a = t.box_base + t.level_off[l] + (i >> (s * (lp - l)));
+            if (has(a)) anc.push_back((int32_t)a);
+          }
+          if (!has(b) && anc.empty()) continue;
+          formed[i] = 1;
+          box[0].push_back((int32_t)b);
+          own[0].push_back(has(b) ? 1 : 0);
+          src[0].push_back(anc);
+        }
+      }
+      const int64_t nl = t.level_off[t.L + 1] - t.level_off[t.L];
+      for (int64_t i = 0; i < nl; ++i) {
+        const int64_t b = t.box_base + t.level_off[t.L] + i;
+        box[1].push_back((int32_t)b);
+        own[1].push_back(has(b) ? 1 : 0);
+        src[1].emplace_back();
+        if (t.L >= 1 && formed[i >> s])
+          src[1].back().push_back((int32_t)(t.box_base + t.level_off[t.L - 1] + (i >> s)));
+      }
+    }
+    for (int k = 0; k < 2; ++k) {
+      size_t need = 1;
+      for (const auto& v : src[k]) need = std::max(need, v.size());
+      int gs = 1;
+      while ((size_t)gs < need) gs <<= 1;
+      if (gs > 16) throw Error{FMM_ENOTSUP, "more than 16 ancestors with M2L pairs"};
+      std::vector<int32_t> flat((size_t)gs * box[k].size(), -1);
+      for (size_t g = 0; g < box[k].size(); ++g)
+        for (size_t j = 0; j < src[k][g].size(); ++j) flat[g * gs + j] = src[k][g][j];
+      FinList& F = L.fin[k];
+      F.gs = gs;
+      F.n = (int64_t)box[k].size();
+      F.box = upload(box[k]);
+      F.own = upload(own[k]);
+      F.anc = upload(flat);
+    }
   }
 }
 

@@ -26,8 +26,10 @@
 //             only atomics are adds to lane-private LDS slots).
 //   M2M:      thread = child box; the 2^s children of a parent sit in
 //             adjacent lanes and are summed with cross-lane shuffles.
-//   L2L:      thread = box of the level; adds the shifted local expansion
-//             of its parent to the box's M2L sum.
+//   L2L:      two launches for all levels: the leaves' parents get their M2L
+//             sum plus the shifted M2L sums of all their ancestors, one lane
+//             per ancestor (local re-centring is exact), summed across
+//             lanes; each leaf then adds its parent's shifted local.
 //   P2M:      block = leaf, thread = point, LDS reduction over points.
 //   L2P:      block = target leaf, thread = target point; writes outputs.
 //   P2P:      block = target leaf, thread = target point; adds the near
@@ -271,37 +273,47 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(
   }
 }
 
-// D[t] = 0 for the boxes t of the list (locals formed without M2L pairs).
-template <typename T>
-__global__ void k_zero_rows(int64_t nb, const int32_t* __restrict__ boxes, int K,
-                            T* __restrict__ D) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nb * K) return;
-  const int64_t i = e / K;
-  D[(int64_t)boxes[i] * K + (e - i * K)] = T(0);
-}
-
 // ---------------------------------------------------------------- L2L
-// D_t += L2L(D_parent) for the boxes of one level (D_t holds the sum of
-// t's M2L translations).
-template <int P, typename T>
-__global__ __launch_bounds__(64) void k_l2l(
-    int64_t nb, const int32_t* __restrict__ boxes, const int32_t* __restrict__ parents,
-    const double* __restrict__ cx, const double* __restrict__ cy,
-    const double* __restrict__ cz, const double* __restrict__ scale,
-    const T* __restrict__ tab, T* D) {
+// Final locals of one list of boxes (FinList): GS lanes per box, lane j
+// translating the expansion anc[j] of src (re-centring a truncated local
+// expansion is exact, so these translations add up to the level-by-level
+// chain), the lanes' results added by a butterfly in a fixed order; the
+// first lane adds the box's own M2L sum (D) and writes the final local to
+// out (the multipole array, free once M2L has run).
+template <int P, typename T, int GS>
+__global__ __launch_bounds__(64) void k_l2l_fin(
+    int64_t nfin, const int32_t* __restrict__ fin_box, const int32_t* __restrict__ fin_own,
+    const int32_t* __restrict__ fin_anc, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz,
+    const double* __restrict__ scale, const T* __restrict__ tab, const T* src,
+    const T* __restrict__ D, T* out) {
   constexpr int K = K_<P>::value;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const int64_t t = boxes[i];
-  const int64_t pa = parents[i];
+  const int64_t g = i / GS;
+  const int j = (int)(i % GS);
+  const bool live = g < nfin;
+  const int64_t t = live ? fin_box[g] : 0;
+  const int a = live ? fin_anc[i] : -1;
   T v[K];
+  if (a >= 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = D[pa * K + k];
-  rotate_shift<P, kL2L, T>(v, cx[pa] - cx[t], cy[pa] - cy[t], cz[pa] - cz[t], scale[pa],
-                           scale[t], tab);
+    for (int k = 0; k < K; ++k) v[k] = src[(int64_t)a * K + k];
+    rotate_shift<P, kL2L, T>(v, cx[a] - cx[t], cy[a] - cy[t], cz[a] - cz[t], scale[a], scale[t],
+                             tab);
+  } else {
 #pragma unroll
-  for (int k = 0; k < K; ++k) D[t * K + k] = D[t * K + k] + v[k];
+    for (int k = 0; k < K; ++k) v[k] = T(0);
+  }
+#pragma unroll
+  for (int off = 1; off < GS; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  if (live && j == 0) {
+    const bool own = fin_own[g] != 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[t * K + k] = (own ? D[t * K + k] : T(0)) + v[k];
+  }
 }
 
 // ---------------------------------------------------------------- L2P
@@ -612,12 +624,25 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
         Ls.seg_lanes, Ls.m2l_src, pl->cx, pl->cy, pl->cz, pl->scale, C, tab, D);
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
-  if (Ls.n_zero > 0)
-    k_zero_rows<T><<<blocks(Ls.n_zero * K_<P>::value, 256), 256, 0, st>>>(
-        Ls.n_zero, Ls.zero_box, K_<P>::value, D);
-  for (const Step& S : TS.l2l_steps)
-    k_l2l<P, T><<<blocks(S.n, 64), 64, 0, st>>>(S.n, S.a, S.b, pl->cx, pl->cy, pl->cz,
-                                                pl->scale, tab, D);
+  // final locals, written over the multipoles: the leaves' parents from all
+  // their ancestors, then the leaves from their parents
+  T* Dfin = C;
+  for (int k = 0; k < 2; ++k) {
+    const FinList& F = Ls.fin[k];
+    if (F.n == 0) continue;
+    const T* from = k == 0 ? D : Dfin;
+    auto l2l = [&](auto kern) {
+      kern<<<blocks(F.n * F.gs, 64), 64, 0, st>>>(F.n, F.box, F.own, F.anc, pl->cx, pl->cy,
+                                                 pl->cz, pl->scale, tab, from, D, Dfin);
+    };
+    switch (F.gs) {
+      case 1: l2l(k_l2l_fin<P, T, 1>); break;
+      case 2: l2l(k_l2l_fin<P, T, 2>); break;
+      case 4: l2l(k_l2l_fin<P, T, 4>); break;
+      case 8: l2l(k_l2l_fin<P, T, 8>); break;
+      default: l2l(k_l2l_fin<P, T, 16>); break;
+    }
+  }
   mk.end(kStL2L, st);
   // near field
   mk.begin(kStP2P, st);
@@ -651,7 +676,7 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   auto l2p = [&](auto kern) {
     kern<<<(unsigned)((nlt + GL - 1) / GL), 64, 0, st>>>(
         nlt, pl->leaf_box + TS.leaf0, pl->leaf_start + TS.leaf0, pl->perm, pl->xs, pl->ys,
-        pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D, tab, n, near, pot, field);
+        pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, Dfin, tab, n, near, pot, field);
   };
   if (field) {
     if (GL == 1) l2p(k_l2p<P, T, true, 1>);

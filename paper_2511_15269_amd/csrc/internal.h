@@ -47,6 +47,17 @@ struct Tables {
   void* dev32 = nullptr;     // device copy (float)
 };
 
+// Boxes whose final local one launch forms: box[g] (own[g]: add its own
+// M2L sum) receives the translations of sources anc[g * gs + j] (-1: none),
+// gs a power of two covering the most sources of any box.
+struct FinList {
+  int32_t* box = nullptr;
+  int32_t* own = nullptr;
+  int32_t* anc = nullptr;
+  int gs = 1;
+  int64_t n = 0;
+};
+
 // Lanes of one M2L block (one wave).
 constexpr int kM2LBlock = 64;
 
@@ -56,9 +67,7 @@ constexpr int kM2LBlock = 64;
 // items of one target consecutive inside one block (item_first[t],
 // item_cnt[t]).  Block b holds the target segments seg_ptr[b] ..
 // seg_ptr[b+1]-1: segment g covers lanes [seg_lanes[g] & 255,
-// seg_lanes[g] >> 8) of target seg_tgt[g].  zero_box lists the boxes whose
-// local is formed but which have no pair in this direction (their M2L sum
-// is zero).
+// seg_lanes[g] >> 8) of target seg_tgt[g].
 struct ListSet {
   int32_t* m2l_ptr = nullptr;  // [nbox+1]
   int32_t* m2l_src = nullptr;  // [n_m2l]
@@ -72,8 +81,13 @@ struct ListSet {
   int32_t* seg_ptr = nullptr;     // [n_blocks+1]
   int32_t* seg_tgt = nullptr;
   int32_t* seg_lanes = nullptr;
-  int32_t* zero_box = nullptr;
-  int64_t n_m2l = 0, n_p2p = 0, n_items = 0, n_blocks = 0, n_zero = 0;
+  // Final locals of the target side in two launches (FinList): fin[0] over
+  // the leaves' parent boxes, each receiving its own M2L sum and the
+  // translations of the M2L sums of all its ancestors with M2L pairs;
+  // fin[1] over the leaves, each receiving its own M2L sum and the
+  // translation of its parent's final local (when the parent has one).
+  FinList fin[2];
+  int64_t n_m2l = 0, n_p2p = 0, n_items = 0, n_blocks = 0;
   // Near-field work items: item j covers direct pairs [pitem_kb[j],
   // pitem_ke[j]) of target leaf pitem_leaf[j], about kP2PItemWork
   // interactions or one whole leaf; every target leaf has at least one.
@@ -258,8 +272,8 @@ struct TreeDesc {
 // the parents h+1 levels above each tree's leaves; L2L step l takes level l
 // of every tree at least that deep.  Boxes outside every M2L pair and
 // without such an ancestor are left out (their expansions are never read,
-// or are zero), except that every leaf gets its local.  Also the boxes of
-// each list direction's target side whose local has no M2L pair.
+// or are zero), except that every leaf gets its local.  Also, per list
+// direction, the ancestors of every target-side leaf whose M2L sums reach it.
 void make_steps(fmm_plan* pl, const std::vector<std::vector<TreeDesc>>& trees, hipStream_t st);
 // Side whose charges a pass in direction dir (0: G-hat, 1: G-hat^T) reads,
 // and side whose points it evaluates.

@@ -347,19 +347,43 @@ fmm_status fmm_plan_set_profiling(fmm_plan* plan, int enable);
 fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
                                  int64_t* passes);
 
-/* Choose the launch tiles of the single-vector evaluation by timing them
- * on this plan: the number of source groups of the near-field kernel
- * (1, 2 or 4) and the number of leaves per wave of P2M and L2P (1, 2, 4 or
- * 8), among the values the plan's largest leaf allows.  Every candidate
- * runs one untimed and three timed evaluations of the charges q (device,
- * [n], the plan's precision) on `stream`; the fastest pair is stored in the
- * plan and used by every later evaluation (results change only by the
- * summation order inside the near field and the multipole sums).  The
- * chosen values are written to *p2p_groups and *leaves_per_wave (host; may
- * be NULL).  Synchronises `stream`; allocates and frees temporary output
+/* Choose the launch tiles of the single-vector evaluation (fmm_tiles) by
+ * timing them on this plan: first the M2L form (one lane or several waves
+ * per translation), then the number of source groups of the near-field
+ * kernel (1, 2 or 4) together with the number of leaves per wave of P2M and
+ * L2P (1, 2, 4 or 8), among the values the plan's largest leaf allows.
+ * Every candidate runs one untimed and three timed evaluations of the
+ * charges q (device, [n], the plan's precision) on `stream`; the fastest
+ * values are stored in the plan and used by every later evaluation
+ * (results change only by the summation order inside the near field and
+ * the multipole sums).  The chosen groups and leaves per wave are written
+ * to *p2p_groups and *leaves_per_wave (host; may be NULL); all three values
+ * can be read with fmm_plan_get_tiles.  Synchronises `stream`; allocates and frees temporary output
  * buffers.  Errors: FMM_EINVAL (NULL plan or q), FMM_ENOMEM, FMM_EDEVICE. */
 fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p2p_groups,
                              int* leaves_per_wave);
+
+/* Launch tiles of the single-vector evaluation, as fmm_plan_autotune
+ * chooses them or a caller sets them:
+ *   p2p_groups       source groups of the near-field kernel: 1, 2 or 4
+ *                    (2 and 4 need leaves of at most 64 / groups points)
+ *   leaves_per_wave  leaves per wave of P2M and L2P: 1, 2, 4 or 8 (at most
+ *                    64 / value points per leaf)
+ *   m2l_waves        waves sharing each M2L translation (Sec. II.D): 1 (one
+ *                    lane per translation) or 4, the shared form, which
+ *                    exists for FP64 at p = 6, 7 and FP32 at p = 9, 10 and
+ *                    is their default.  Both forms give identical results.
+ * fmm_plan_set_tiles takes 0 in a field as "the default for this plan" and
+ * rejects any other value the plan cannot use (FMM_EINVAL, plan unchanged).
+ * fmm_plan_get_tiles writes the values evaluations use (host *tiles).
+ * Neither call touches the device. */
+typedef struct fmm_tiles {
+  int p2p_groups;
+  int leaves_per_wave;
+  int m2l_waves;
+} fmm_tiles;
+fmm_status fmm_plan_set_tiles(fmm_plan* plan, const fmm_tiles* tiles);
+fmm_status fmm_plan_get_tiles(const fmm_plan* plan, fmm_tiles* tiles);
 
 /* Release the plan and its device memory (NULL is accepted). */
 fmm_status fmm_plan_destroy(fmm_plan* plan);

@@ -19,7 +19,8 @@ import torch
 
 from ._lib import (ALLOC_FN, FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_PLAN_NO_WORKSPACE,
                    FMM_TIE_SOURCE, FMM_TIE_TARGET,
-                   FREE_FN, STAGES, FmmAllocator, FMMError, FmmParams, FmmPlanInfo, check, lib)
+                   FREE_FN, STAGES, FmmAllocator, FMMError, FmmParams, FmmPlanInfo, FmmTiles,
+                   check, lib)
 
 __all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotential",
            "fmm_energy", "workspace_bytes", "torch_allocator"]
@@ -320,7 +321,20 @@ class Plan:
             check(lib().fmm_plan_autotune(self._h, ctypes.c_void_p(qq.data_ptr()),
                                           _stream_ptr(None), ctypes.byref(g),
                                           ctypes.byref(lw)))
-        return {"p2p_groups": g.value, "leaves_per_wave": lw.value}
+        return self.tiles()
+
+    def tiles(self) -> dict:
+        """Launch tiles the evaluations use (fmm_plan_get_tiles)."""
+        t = FmmTiles()
+        check(lib().fmm_plan_get_tiles(self._h, ctypes.byref(t)))
+        return {"p2p_groups": t.p2p_groups, "leaves_per_wave": t.leaves_per_wave,
+                "m2l_waves": t.m2l_waves}
+
+    def set_tiles(self, p2p_groups: int = 0, leaves_per_wave: int = 0,
+                  m2l_waves: int = 0) -> None:
+        """Set the launch tiles (0: the plan's default; fmm_plan_set_tiles)."""
+        t = FmmTiles(p2p_groups, leaves_per_wave, m2l_waves)
+        check(lib().fmm_plan_set_tiles(self._h, ctypes.byref(t)))
 
     def set_profiling(self, on: bool = True) -> None:
         """Record per-stage HIP events in every evaluate (see

@@ -37,6 +37,11 @@ class FmmPlanInfo(ctypes.Structure):
                 ("p2p_items", ctypes.c_int64)]
 
 
+class FmmTiles(ctypes.Structure):
+    _fields_ = [("p2p_groups", ctypes.c_int), ("leaves_per_wave", ctypes.c_int),
+                ("m2l_waves", ctypes.c_int)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -95,7 +100,9 @@ def lib() -> ctypes.CDLL:
         L.fmm_graph_destroy.argtypes = [vp]
         L.fmm_plan_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int)]
-        for f in ("fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
+        L.fmm_plan_set_tiles.argtypes = [vp, ctypes.POINTER(FmmTiles)]
+        L.fmm_plan_get_tiles.argtypes = [vp, ctypes.POINTER(FmmTiles)]
+        for f in ("fmm_plan_set_tiles", "fmm_plan_get_tiles", "fmm_plan_create", "fmm_plan_get_info", "fmm_evaluate",
                   "fmm_plan_get_tree", "fmm_plan_get_lists", "fmm_plan_destroy",
                   "fmm_direct", "fmm_plan_set_profiling", "fmm_plan_read_profile",
                   "fmm_evaluate_transposed", "fmm_adjoint", "fmm_multi_plan_create",

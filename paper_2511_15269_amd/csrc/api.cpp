@@ -825,7 +825,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     void* fld = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = pl->profiling;
-    const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave;
+    const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave, w0 = pl->m2l_waves;
     auto cleanup = [&] {
       if (pot || fld) (void)hipStreamSynchronize(st);
       dev_free(pl, pot);
@@ -840,6 +840,23 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
       FMM_HIP(hipEventCreate(&e0));
       FMM_HIP(hipEventCreate(&e1));
       pl->profiling = false;
+      auto time3 = [&] {
+        fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
+        FMM_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
+        FMM_HIP(hipEventRecord(e1, st));
+        FMM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        FMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+      };
+      if (m2l_share_waves(pl->prm.p, pl->prm.precision == FMM_FP64) > 1) {
+        pl->m2l_waves = 1;
+        const float one = time3();
+        pl->m2l_waves = 0;
+        const float shared = time3();
+        pl->m2l_waves = one < shared ? 1 : 0;
+      }
       float best = -1.f;
       int bg = 0, bl = 0;
       for (int g : {1, 2, 4}) {
@@ -848,13 +865,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
           if (!valid_leaves_per_wave(pl, l)) continue;
           pl->p2p_groups = g;
           pl->leaves_per_wave = l;
-          fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
-          FMM_HIP(hipEventRecord(e0, st));
-          for (int r = 0; r < 3; ++r) fmm::evaluate(pl, pl->ws, 0, q, 1, pot, fld, st);
-          FMM_HIP(hipEventRecord(e1, st));
-          FMM_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          FMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const float ms = time3();
           if (best < 0.f || ms < best) {
             best = ms;
             bg = g;
@@ -867,12 +878,41 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     } catch (...) {
       pl->p2p_groups = g0;
       pl->leaves_per_wave = l0;
+      pl->m2l_waves = w0;
       cleanup();
       throw;
     }
     cleanup();
     if (groups_out) *groups_out = pl->p2p_groups;
     if (leaves_out) *leaves_out = pl->leaves_per_wave;
+  });
+}
+
+fmm_status fmm_plan_set_tiles(fmm_plan* pl, const fmm_tiles* t) {
+  return guard([&] {
+    if (!pl || !t) throw Error{FMM_EINVAL, "plan and tiles must not be NULL"};
+    if (t->p2p_groups != 0 && !valid_p2p_groups(pl, t->p2p_groups))
+      throw Error{FMM_EINVAL, "p2p_groups must be 0, 1, 2 or 4 and fit the largest leaf"};
+    if (t->leaves_per_wave != 0 && !valid_leaves_per_wave(pl, t->leaves_per_wave))
+      throw Error{FMM_EINVAL, "leaves_per_wave must be 0, 1, 2, 4 or 8 and fit the largest leaf"};
+    const int shared = m2l_share_waves(pl->prm.p, pl->prm.precision == FMM_FP64);
+    if (t->m2l_waves != 0 && t->m2l_waves != 1 && t->m2l_waves != shared)
+      throw Error{FMM_EINVAL, shared > 1 ? "m2l_waves must be 0, 1 or " + std::to_string(shared) +
+                                               " for this order and precision"
+                                         : std::string("m2l_waves must be 0 or 1 for this "
+                                                       "order and precision")};
+    pl->p2p_groups = t->p2p_groups;
+    pl->leaves_per_wave = t->leaves_per_wave;
+    pl->m2l_waves = t->m2l_waves == 1 ? 1 : 0;
+  });
+}
+
+fmm_status fmm_plan_get_tiles(const fmm_plan* pl, fmm_tiles* t) {
+  return guard([&] {
+    if (!pl || !t) throw Error{FMM_EINVAL, "plan and tiles must not be NULL"};
+    t->p2p_groups = p2p_groups(pl);
+    t->leaves_per_wave = leaves_per_wave(pl);
+    t->m2l_waves = m2l_waves(pl);
   });
 }
 

@@ -248,8 +248,13 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(
     for (int k = 0; k < KL; ++k)
       __hip_atomic_fetch_add(&accl[k * kRow + lane], v[k], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    {
+      // a plain add: whether the compiler would fuse it with the last
+      // product of the translation depends on the surrounding code
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int k = KL; k < K; ++k) acc[k - KL] += v[k];
+      for (int k = KL; k < K; ++k) acc[k - KL] += v[k];
+    }
   }
   const int sb = seg_ptr[b], se = seg_ptr[b + 1];
   __syncthreads();
@@ -271,6 +276,163 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(
                                                    seg_lanes, D);
     __syncthreads();
   }
+}
+
+// The same M2L items with the translation of each item shared by the NW
+// waves of a block: lane l of every wave works on item l.  The rotations
+// act degree by degree and the z-shift order by order, so wave w rotates
+// the degrees of share_mask(P, NW, w, false) and z-shifts the orders of
+// share_mask(P, NW, w, true), the coefficients passing between the two
+// through a 64-lane LDS tile (three barriers per translation).  Every
+// coefficient undergoes the same operations in the same order as in k_m2l,
+// so the two kernels give identical results; the waves of the shared form
+// hold a fraction of the coefficients each, which lets more of them share a
+// SIMD and shortens each wave's chain of dependent operations.
+
+// Multiply-adds of the two rotation phases on degree n (Y products and
+// azimuth steps) and of the M2L z-shift of orders +-am.
+__host__ __device__ constexpr int rot_cost(int n) { return 4 * (n * n + n + 1) + 16 * n; }
+__host__ __device__ constexpr int shift_cost(int P, int am) {
+  return (am > 0 ? 2 : 1) * (P + 1 - am) * (P + 1 - am);
+}
+
+// Degrees (orders: false/true) of wave w: largest cost first, each onto the
+// least loaded wave (the first of equals).
+__host__ __device__ constexpr unsigned share_mask(int P, int NW, int w, bool orders) {
+  int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned done = 0;
+  for (int step = 0; step <= P; ++step) {
+    int pick = -1, pc = -1;
+    for (int x = 0; x <= P; ++x) {
+      if ((done >> x) & 1u) continue;
+      const int c = orders ? shift_cost(P, x) : rot_cost(x);
+      if (c > pc) {
+        pc = c;
+        pick = x;
+      }
+    }
+    done |= 1u << pick;
+    int best = 0;
+    for (int j = 1; j < NW; ++j)
+      if (load[j] < load[best]) best = j;
+    load[best] += pc;
+    mask[best] |= 1u << pick;
+  }
+  return mask[w];
+}
+
+template <int P, typename T, int NW, int W>
+__device__ __forceinline__ void m2l_share(int lane, int jb, int je, int iters, double tx,
+                                          double ty, double tz, double rt,
+                                          const int32_t* __restrict__ src,
+                                          const double* __restrict__ cx,
+                                          const double* __restrict__ cy,
+                                          const double* __restrict__ cz,
+                                          const double* __restrict__ scale,
+                                          const T* __restrict__ C, const T* __restrict__ tab,
+                                          T* X) {
+  constexpr int K = K_<P>::value;
+  constexpr unsigned DM = share_mask(P, NW, W, false);
+  constexpr unsigned OM = share_mask(P, NW, W, true);
+  // coefficient loops over (n, m): k = cidx(n, m) of the wave's degrees
+  // (DM) or orders (OM)
+#define FMM_DEG_LOOP(stmt)                                  \
+  _Pragma("unroll") for (int n = 0; n <= P; ++n) {          \
+    if (!((DM >> n) & 1u)) continue;                        \
+    _Pragma("unroll") for (int m = -n; m <= n; ++m) {       \
+      const int k = cidx(n, m);                             \
+      stmt;                                                 \
+    }                                                       \
+  }
+#define FMM_ORD_LOOP(stmt)                                  \
+  _Pragma("unroll") for (int n = 0; n <= P; ++n) {          \
+    _Pragma("unroll") for (int m = -n; m <= n; ++m) {       \
+      if (!((OM >> (m < 0 ? -m : m)) & 1u)) continue;       \
+      const int k = cidx(n, m);                             \
+      stmt;                                                 \
+    }                                                       \
+  }
+  T acc[K];
+  FMM_DEG_LOOP(acc[k] = T(0))
+  for (int it = 0; it < iters; ++it) {
+    const int j = jb + it;
+    const bool act = j < je;
+    const int sidx = act ? src[j] : 0;
+    const Turn<P, kM2L, T> g(cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, scale[sidx], rt);
+    T v[K];
+    if (act) {
+      FMM_DEG_LOOP(v[k] = C[(int64_t)sidx * K + k])
+      turn_forward<P, kM2L, T, DM>(v, g, tab);
+      FMM_DEG_LOOP(X[k * kRow + lane] = v[k])
+    }
+    __syncthreads();
+    if (act) {
+      T z[K];
+      FMM_ORD_LOOP(z[k] = X[k * kRow + lane])
+      zshift<P, kM2L, T, OM>(z, g.a, g.b, tab);
+      FMM_ORD_LOOP(X[k * kRow + lane] = z[k])
+    }
+    __syncthreads();
+    if (act) {
+      FMM_DEG_LOOP(v[k] = X[k * kRow + lane])
+    }
+    __syncthreads();
+    if (act) {
+      turn_back<P, kM2L, T, DM>(v, g, tab);
+      {
+        // a plain add, as in k_m2l
+#pragma clang fp contract(off)
+        FMM_DEG_LOOP(acc[k] += v[k])
+      }
+    }
+  }
+  FMM_DEG_LOOP(X[k * kRow + lane] = acc[k])
+#undef FMM_DEG_LOOP
+#undef FMM_ORD_LOOP
+}
+
+template <int P, typename T, int NW>
+__global__ __launch_bounds__(kM2LBlock * NW) void k_m2l_shared(
+    int64_t nblocks, const int32_t* __restrict__ item_tgt,
+    const int32_t* __restrict__ item_begin, const int32_t* __restrict__ item_end,
+    const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ seg_tgt,
+    const int32_t* __restrict__ seg_lanes, const int32_t* __restrict__ src,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ C, const T* __restrict__ tab, T* __restrict__ D) {
+  constexpr int K = K_<P>::value;
+  __shared__ T X[(K - 1) * kRow + kM2LBlock];
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x % kM2LBlock;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kM2LBlock);
+  const int64_t i = b * kM2LBlock + lane;
+  const int t = item_tgt[i];
+  const int jb = item_begin[i], je = item_end[i];  // empty for idle lanes
+  const int tt = t < 0 ? 0 : t;
+  const double tx = cx[tt], ty = cy[tt], tz = cz[tt], rt = scale[tt];
+  // translations of the longest item of the block (the same in every wave)
+  int iters = je - jb;
+#pragma unroll
+  for (int off = 1; off < kM2LBlock; off <<= 1) iters = max(iters, __shfl_xor(iters, off, 64));
+  iters = __builtin_amdgcn_readfirstlane(iters);
+#define FMM_M2L_WAVE(W)                                                                   \
+  case W:                                                                                 \
+    if constexpr (W < NW)                                                                 \
+      m2l_share<P, T, NW, W>(lane, jb, je, iters, tx, ty, tz, rt, src, cx, cy, cz, scale, \
+                             C, tab, X);                                                  \
+    break;
+  static_assert(NW <= 4, "at most four waves per translation");
+  switch (w) {
+    FMM_M2L_WAVE(0)
+    FMM_M2L_WAVE(1)
+    FMM_M2L_WAVE(2)
+    FMM_M2L_WAVE(3)
+    default: break;
+  }
+#undef FMM_M2L_WAVE
+  __syncthreads();
+  segment_sums<K, T>(X, 0, K, seg_ptr[b], seg_ptr[b + 1], seg_tgt, seg_lanes, D);
 }
 
 // ---------------------------------------------------------------- L2L
@@ -618,10 +780,22 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   }
   mk.end(kStM2M, st);
   mk.begin(kStM2L, st);
-  if (Ls.n_blocks > 0)
-    k_m2l<P, T><<<(unsigned)Ls.n_blocks, kM2LBlock, 0, st>>>(
-        Ls.n_blocks, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.seg_ptr, Ls.seg_tgt,
-        Ls.seg_lanes, Ls.m2l_src, pl->cx, pl->cy, pl->cz, pl->scale, C, tab, D);
+  if (Ls.n_blocks > 0) {
+    auto m2l = [&](auto kern, int nw) {
+      kern<<<(unsigned)Ls.n_blocks, kM2LBlock * nw, 0, st>>>(
+          Ls.n_blocks, Ls.item_tgt, Ls.item_begin, Ls.item_end, Ls.seg_ptr, Ls.seg_tgt,
+          Ls.seg_lanes, Ls.m2l_src, pl->cx, pl->cy, pl->cz, pl->scale, C, tab, D);
+    };
+    constexpr int NW = m2l_share_waves(P, sizeof(T) == 8);
+    if constexpr (NW > 1) {
+      if (m2l_waves(pl) > 1)
+        m2l(k_m2l_shared<P, T, NW>, NW);
+      else
+        m2l(k_m2l<P, T>, 1);
+    } else {
+      m2l(k_m2l<P, T>, 1);
+    }
+  }
   mk.end(kStM2L, st);
   mk.begin(kStL2L, st);
   // final locals, written over the multipoles: the leaves' parents from all
@@ -705,6 +879,10 @@ int p2p_groups(const fmm_plan* pl) {
   if (pl->p2p_groups && valid_p2p_groups(pl, pl->p2p_groups)) return pl->p2p_groups;
   const int m = pl->max_leaf_count;
   return m > 32 ? 1 : (m > 16 ? 2 : 4);
+}
+int m2l_waves(const fmm_plan* pl) {
+  const int shared = m2l_share_waves(pl->prm.p, pl->prm.precision == FMM_FP64);
+  return pl->m2l_waves == 1 ? 1 : shared;
 }
 int leaves_per_wave(const fmm_plan* pl) {
   if (pl->leaves_per_wave && valid_leaves_per_wave(pl, pl->leaves_per_wave))

@@ -192,6 +192,9 @@ struct fmm_plan {
   // fmm_plan_autotune): P2P source groups, P2M/L2P leaves per wave
   int p2p_groups = 0;
   int leaves_per_wave = 0;
+  // 1: one lane per M2L translation; 0: the shared form where it is built
+  // (m2l_share_waves), else one lane
+  int m2l_waves = 0;
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   int nsides = 1;               // 2: separate sources (side 0) and targets (side 1)
   fmm::Side side[2];
@@ -322,6 +325,16 @@ void direct_sum(int64_t n, const double* pos, const void* q, int precision,
 // needs max_leaf_count <= 64 / leaves).
 int p2p_groups(const fmm_plan* pl);
 int leaves_per_wave(const fmm_plan* pl);
+int m2l_waves(const fmm_plan* pl);
+// Waves per translation of the shared M2L form for order p and precision
+// (1: no shared form).  It is built where it was measured faster than one
+// lane per translation: FP64 at p = 6, 7 (above, its LDS tile caps the
+// occupancy; below, one lane per translation keeps two waves per SIMD
+// anyway) and FP32 at p = 9, 10 (where the one-lane form runs out of
+// registers).
+constexpr int m2l_share_waves(int p, bool fp64) {
+  return fp64 ? ((p == 6 || p == 7) ? 4 : 1) : (p >= 9 ? 4 : 1);
+}
 bool valid_p2p_groups(const fmm_plan* pl, int g);
 bool valid_leaves_per_wave(const fmm_plan* pl, int l);
 

@@ -65,44 +65,56 @@ struct TabReader {
   }
 };
 
-// cos(m g), sin(m g), m = 0..P, by repeated complex multiplication
-template <int P, typename T>
-__device__ __forceinline__ void powers(T c1, T s1, T* c, T* s) {
-  c[0] = T(1);
-  s[0] = T(0);
-#pragma unroll
-  for (int m = 1; m <= P; ++m) {
-    c[m] = c[m - 1] * c1 - s[m - 1] * s1;
-    s[m] = s[m - 1] * c1 + c[m - 1] * s1;
-  }
-}
+// The translation steps below (azimuth, apply_y, zshift, Turn) do not let
+// the compiler fuse a product with an addition on its own: every fused
+// multiply-add is written out, so the rounding of each coefficient is fixed
+// by the source and the same wherever the steps are inlined (the one-lane
+// and the wave-shared M2L forms give identical results).
+//
+// Degree masks (bit n: degree n) and order masks (bit |m|: orders +-m)
+// restrict the steps to part of a coefficient vector; the default takes all
+// of it.
+template <int P>
+struct All_ {
+  static constexpr unsigned value = (1u << (P + 1)) - 1u;
+};
 
 // (v^m, v^{-m}) <- (a c + b s, b c - a s) for every degree, with
-// (c, s) = (cm[m], sgn * sm[m]) after the quarter-turn shift q (m*q*pi/2
-// added to the angle; q in {0, 1}): q = 1 maps (cos ma, sin ma) to
-// (cos m(pi/2 - a), sin m(pi/2 - a)).
-template <int P, typename T, int SGN, int Q>
-__device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
+// (c, s) = (cos m g, sgn sin m g) after the quarter-turn shift q (m*q*pi/2
+// added to the angle; q in {0, 1}): q = 1 maps (cos mg, sin mg) to
+// (cos m(pi/2 - g), sin m(pi/2 - g)).  cos m g and sin m g are formed from
+// (c1, s1) = (cos g, sin g) by repeated complex multiplication as m grows
+// (the same values at every call, and no registers held between calls).
+template <int P, typename T, int SGN, int Q, unsigned DM = All_<P>::value>
+__device__ __forceinline__ void azimuth(T* v, T c1, T s1) {
+#pragma clang fp contract(off)
+  T cm = T(1), sm = T(0);
 #pragma unroll
   for (int m = 1; m <= P; ++m) {
+    if ((DM >> m) == 0) break;  // no degree >= m in the mask
+    const T cn = fma(cm, c1, -(sm * s1));
+    const T sn = fma(sm, c1, cm * s1);
+    cm = cn;
+    sm = sn;
     T c, s;
     if (Q == 0) {
-      c = cm[m];
-      s = sm[m];
+      c = cm;
+      s = sm;
     } else {
       switch (m & 3) {
-        case 0: c = cm[m]; s = -sm[m]; break;
-        case 1: c = sm[m]; s = cm[m]; break;
-        case 2: c = -cm[m]; s = sm[m]; break;
-        default: c = -sm[m]; s = -cm[m]; break;
+        case 0: c = cm; s = -sm; break;
+        case 1: c = sm; s = cm; break;
+        case 2: c = -cm; s = sm; break;
+        default: c = -sm; s = -cm; break;
       }
     }
     if (SGN < 0) s = -s;
 #pragma unroll
     for (int n = m; n <= P; ++n) {
+      if (!((DM >> n) & 1u)) continue;
       T a = v[cidx(n, m)], b = v[cidx(n, -m)];
-      v[cidx(n, m)] = a * c + b * s;
-      v[cidx(n, -m)] = b * c - a * s;
+      v[cidx(n, m)] = fma(a, c, b * s);
+      v[cidx(n, -m)] = fma(b, c, -(a * s));
     }
   }
 }
@@ -111,13 +123,23 @@ __device__ __forceinline__ void azimuth(T* v, const T* cm, const T* sm) {
 // column: each input coefficient is scattered into the output rows it
 // reaches, so consecutive multiply-adds go to different accumulators.  The
 // column-major order of Y_n is the row-major order of Y_n^T, so the product
-// with Y_n reads the stored Y_n^T rows and vice versa.
-template <int P, bool TR, typename T>
+// with Y_n reads the stored Y_n^T rows and vice versa.  A run of consecutive
+// degrees in the mask is read with one sequential table reader.  (The
+// reader of degree 1 is set up even when degree 1 is not in the mask; its
+// loads go unused.)
+template <int P, bool TR, typename T, unsigned DM = All_<P>::value>
 __device__ __forceinline__ void apply_y(T* v, const T* __restrict__ tab) {
-  TabReader<T> Y(local_ptr(tab) + (TR ? tab_y(P) : tab_yt(P)) + ycbase(1));
+#pragma clang fp contract(off)
+  const T* base = tab + (TR ? tab_y(P) : tab_yt(P));
+  TabReader<T> Y(local_ptr(base) + ycbase(1));
   int o = 0;
 #pragma unroll
   for (int n = 1; n <= P; ++n) {
+    if (!((DM >> n) & 1u)) continue;
+    if (n > 1 && !((DM >> (n - 1)) & 1u)) {  // a new run of degrees
+      Y = TabReader<T>(local_ptr(base) + ycbase(n));
+      o = 0;
+    }
     T u[2 * P + 1];
     bool live[2 * P + 1];
 #pragma unroll
@@ -146,8 +168,9 @@ enum { kM2M = 0, kM2L = 1, kL2L = 2 };
 //   M2L (a = rho_src/r, b = rho_tgt/r):   out_n = b^{n+1} sum_k T_nk a^k v_k
 //   M2M (a = r/rho_par, b = rho_chi/rho_par): out_n = sum_{k<=n} T_nk a^{n-k} b^k v_k
 //   L2L (a = r/rho_par, b = rho_chi/rho_par): out_n = b^{n+1} sum_{k>=n} T_nk a^{k-n} v_k
-template <int P, int KIND, typename T>
+template <int P, int KIND, typename T, unsigned OM = All_<P>::value>
 __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab) {
+#pragma clang fp contract(off)
   T pa[2 * P + 2], pb[P + 2];
   pa[0] = T(1);
   pb[0] = T(1);
@@ -159,12 +182,14 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
 #pragma unroll
     for (int n = 0; n <= P; ++n)
 #pragma unroll
-      for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pa[n];
+      for (int m = -n; m <= n; ++m)
+        if ((OM >> (m < 0 ? -m : m)) & 1u) v[cidx(n, m)] *= pa[n];
     // table column by column (k outer): independent accumulators; the
     // blocks of -m and +m are the same, read twice in a row
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
+      if (!((OM >> am) & 1u)) continue;
       TabReader<T> tb(local_ptr(tab) + tab_tm2l(P) + zl_base(P, am));
       T o[P + 1];
       int c = 0;
@@ -186,11 +211,13 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
 #pragma unroll
       for (int n = 0; n <= P; ++n)
 #pragma unroll
-        for (int m = -n; m <= n; ++m) v[cidx(n, m)] *= pb[n];
+        for (int m = -n; m <= n; ++m)
+          if ((OM >> (m < 0 ? -m : m)) & 1u) v[cidx(n, m)] *= pb[n];
     }
 #pragma unroll
     for (int m = -P; m <= P; ++m) {
       const int am = m < 0 ? -m : m;
+      if (!((OM >> am) & 1u)) continue;
       TabReader<T> tb(local_ptr(tab) + (KIND == kM2M ? tab_tm2m(P) : tab_tl2l(P)) +
                       zt_base(P, am));
       T o[P + 1];
@@ -220,6 +247,83 @@ __device__ __forceinline__ void zshift(T* v, T a, T b, const T* __restrict__ tab
   }
 }
 
+// Geometry of one translation: b = old centre - new centre, rho_old and
+// rho_new the scale lengths of the two boxes.  Holds cosine and sine of the
+// two rotation angles (azimuth A of b, polar angle B) and the z-shift
+// ratios (a, b of zshift).
+template <int P, int KIND, typename T>
+struct Turn {
+  T ca, sa, cb, sb;
+  T a, b;
+  __device__ __forceinline__ Turn(double bx, double by, double bz, double rho_old,
+                                  double rho_new) {
+#pragma clang fp contract(off)
+    const double rxy2 = bx * bx + by * by;
+    const double rxy = sqrt(rxy2);
+    const double r = sqrt(rxy2 + bz * bz);
+    // two reciprocals instead of six divisions
+    const double ixy = rxy > 0.0 ? 1.0 / rxy : 0.0;
+    const double ir = r > 0.0 ? 1.0 / r : 0.0;
+    double dca = 1.0, dsa = 0.0, dcb = 1.0, dsb = 0.0;
+    if (rxy > 0.0) {
+      dca = bx * ixy;
+      dsa = by * ixy;
+    }
+    if (r > 0.0) {
+      dcb = bz * ir;
+      dsb = rxy * ir;
+    }
+    double da, db;
+    if (KIND == kM2L) {
+      da = rho_old * ir;
+      db = rho_new * ir;
+    } else {
+      const double ip = 1.0 / (KIND == kM2M ? rho_new : rho_old);
+      da = r * ip;
+      db = (KIND == kM2M ? rho_old : rho_new) * ip;
+    }
+    a = T(da);
+    b = T(db);
+    ca = T(dca);
+    sa = T(dsa);
+    cb = T(dcb);
+    sb = T(dsb);
+  }
+};
+
+// Rotation taking b onto +z: Rz(pi/2 - A), Y, Rz(-B), Y^T (sign
+// conventions per kind), on the degrees of DM.
+template <int P, int KIND, typename T, unsigned DM = All_<P>::value>
+__device__ __forceinline__ void turn_forward(T* v, const Turn<P, KIND, T>& g,
+                                             const T* __restrict__ tab) {
+  if (KIND == kL2L)
+    azimuth<P, T, -1, 1, DM>(v, g.ca, g.sa);
+  else
+    azimuth<P, T, +1, 1, DM>(v, g.ca, g.sa);
+  apply_y<P, false, T, DM>(v, tab);
+  if (KIND == kL2L)
+    azimuth<P, T, +1, 0, DM>(v, g.cb, g.sb);
+  else
+    azimuth<P, T, -1, 0, DM>(v, g.cb, g.sb);
+  apply_y<P, true, T, DM>(v, tab);
+}
+
+// The inverse rotation: Y, Rz(B), Y^T, Rz(A - pi/2), on the degrees of DM.
+template <int P, int KIND, typename T, unsigned DM = All_<P>::value>
+__device__ __forceinline__ void turn_back(T* v, const Turn<P, KIND, T>& g,
+                                          const T* __restrict__ tab) {
+  apply_y<P, false, T, DM>(v, tab);
+  if (KIND == kM2M)
+    azimuth<P, T, +1, 0, DM>(v, g.cb, g.sb);
+  else
+    azimuth<P, T, -1, 0, DM>(v, g.cb, g.sb);
+  apply_y<P, true, T, DM>(v, tab);
+  if (KIND == kM2M)
+    azimuth<P, T, -1, 1, DM>(v, g.ca, g.sa);
+  else
+    azimuth<P, T, +1, 1, DM>(v, g.ca, g.sa);
+}
+
 // Rotate so that b points along +z, shift along z, rotate back.
 // b = old centre - new centre; rho_old, rho_new the scale lengths of the
 // two boxes.  M2L maps multipole (regular-basis sign convention) to local
@@ -228,55 +332,10 @@ template <int P, int KIND, typename T>
 __device__ __forceinline__ void rotate_shift(T* v, double bx, double by, double bz,
                                              double rho_old, double rho_new,
                                              const T* __restrict__ tab) {
-  const double rxy2 = bx * bx + by * by;
-  const double rxy = sqrt(rxy2);
-  const double r = sqrt(rxy2 + bz * bz);
-  double ca = 1.0, sa = 0.0, cb = 1.0, sb = 0.0;
-  if (rxy > 0.0) {
-    ca = bx / rxy;
-    sa = by / rxy;
-  }
-  if (r > 0.0) {
-    cb = bz / r;
-    sb = rxy / r;
-  }
-  double a, b;
-  if (KIND == kM2L) {
-    a = rho_old / r;
-    b = rho_new / r;
-  } else if (KIND == kM2M) {
-    a = r / rho_new;
-    b = rho_old / rho_new;
-  } else {
-    a = r / rho_old;
-    b = rho_new / rho_old;
-  }
-  T am_c[P + 1], am_s[P + 1], bm_c[P + 1], bm_s[P + 1];
-  powers<P, T>(T(ca), T(sa), am_c, am_s);
-  powers<P, T>(T(cb), T(sb), bm_c, bm_s);
-  // forward: Rz(pi/2 - A), Y, Rz(-B), Y^T   (sign conventions per kind)
-  if (KIND == kL2L)
-    azimuth<P, T, -1, 1>(v, am_c, am_s);
-  else
-    azimuth<P, T, +1, 1>(v, am_c, am_s);
-  apply_y<P, false, T>(v, tab);
-  if (KIND == kL2L)
-    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
-  else
-    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
-  apply_y<P, true, T>(v, tab);
-  zshift<P, KIND, T>(v, T(a), T(b), tab);
-  // back: Y, Rz(B), Y^T, Rz(A - pi/2)
-  apply_y<P, false, T>(v, tab);
-  if (KIND == kM2M)
-    azimuth<P, T, +1, 0>(v, bm_c, bm_s);
-  else
-    azimuth<P, T, -1, 0>(v, bm_c, bm_s);
-  apply_y<P, true, T>(v, tab);
-  if (KIND == kM2M)
-    azimuth<P, T, -1, 1>(v, am_c, am_s);
-  else
-    azimuth<P, T, +1, 1>(v, am_c, am_s);
+  const Turn<P, KIND, T> g(bx, by, bz, rho_old, rho_new);
+  turn_forward<P, KIND, T>(v, g, tab);
+  zshift<P, KIND, T>(v, g.a, g.b, tab);
+  turn_back<P, KIND, T>(v, g, tab);
 }
 
 // Source points in leaf order with their charges, one 32-byte record per

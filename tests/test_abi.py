@@ -196,3 +196,11 @@ def test_create_st_checks_arguments_first():
     assert lib.fmm_plan_create_st(d, 10, d, 10, ctypes.byref(_prm(p=12)), None, 0, None,
                                   ctypes.byref(out)) == L.FMM_ENOTSUP
     assert out.value == 55
+
+
+def test_tiles_null_arguments():
+    lib = L.lib()
+    t = L.FmmTiles(1, 1, 1)
+    assert lib.fmm_plan_set_tiles(None, ctypes.byref(t)) == L.FMM_EINVAL
+    assert lib.fmm_plan_get_tiles(None, ctypes.byref(t)) == L.FMM_EINVAL
+    assert (t.p2p_groups, t.leaves_per_wave, t.m2l_waves) == (1, 1, 1)

@@ -507,10 +507,52 @@ def test_autotuned_tiles_give_the_same_results(fmm, prec, n, leaf, s, tol):
     choice = b.autotune(qt)
     _say(f"    chosen {choice}")
     assert choice["p2p_groups"] in (1, 2, 4) and choice["leaves_per_wave"] in (1, 2, 4, 8)
+    assert choice["m2l_waves"] in ((1, 4) if prec == "fp64" else (1,))
     ua, fa = a.evaluate(qt)
     ub, fb = b.evaluate(qt)
     assert _rel(ub.double().cpu().numpy(), ua.double().cpu().numpy()) <= tol
     assert _rel(fb.double().cpu().numpy(), fa.double().cpu().numpy()) <= tol
+
+
+@pytest.mark.parametrize("prec,p,n,leaf,s,theta", [
+    ("fp64", 6, 30000, 64, 2, 0.5), ("fp64", 7, 40000, 64, 3, 0.8),
+    ("fp32", 9, 30000, 64, 3, 0.7), ("fp32", 10, 20000, 32, 2, 0.6)])
+def test_m2l_shared_form_is_identical_to_one_lane_form(fmm, prec, p, n, leaf, s, theta):
+    """The M2L form whose translations are shared by several waves applies
+    the same operations to every coefficient in the same order as the form
+    with one lane per translation: forward and transposed results agree
+    bit for bit."""
+    _say(f"[m2l forms] {prec} p={p} n={n} leaf={leaf} s={s} theta={theta}")
+    pos, q = workloads.clustered(n, 90 + p)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda().to(dt)
+    plan = fmm.Plan(pt, p=p, leaf_max=leaf, splits=s, theta=theta, precision=prec)
+    assert plan.tiles()["m2l_waves"] == 4
+    u1, f1 = plan.evaluate(qt)
+    t1 = plan.evaluate_transposed(qt)
+    plan.set_tiles(m2l_waves=1)
+    assert plan.tiles()["m2l_waves"] == 1
+    u0, f0 = plan.evaluate(qt)
+    t0 = plan.evaluate_transposed(qt)
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1) and torch.equal(f0, f1)
+    assert torch.equal(t0[0], t1[0]) and torch.equal(t0[1], t1[1])
+    with pytest.raises(fmm.FMMError):
+        plan.set_tiles(m2l_waves=3)
+    assert plan.tiles()["m2l_waves"] == 1
+
+
+def test_m2l_one_lane_form_where_no_shared_form_is_built(fmm):
+    pos, _ = workloads.uniform_cube(5000, 3)
+    pt = torch.from_numpy(pos).cuda()
+    for prec, p in (("fp64", 8), ("fp64", 5), ("fp32", 8)):
+        plan = fmm.Plan(pt, p=p, leaf_max=64, splits=3, theta=0.7, precision=prec)
+        assert plan.tiles()["m2l_waves"] == 1
+        with pytest.raises(fmm.FMMError):
+            plan.set_tiles(m2l_waves=4)
+        plan.set_tiles(m2l_waves=1)
+        assert plan.tiles()["m2l_waves"] == 1
 
 
 @pytest.mark.parametrize("prec,n,p,leaf,s,theta", [("fp64", 30000, 5, 64, 2, 0.6),

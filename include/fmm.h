@@ -348,8 +348,8 @@ fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
                                  int64_t* passes);
 
 /* Choose the launch tiles of the single-vector evaluation (fmm_tiles) by
- * timing them on this plan: first the M2L form (one lane or several waves
- * per translation), then the number of source groups of the near-field
+ * timing them on this plan: first the M2L form and the M2M / L2L form (one
+ * lane or several waves per translation), then the number of source groups of the near-field
  * kernel (1, 2 or 4) together with the number of leaves per wave of P2M and
  * L2P (1, 2, 4 or 8), among the values the plan's largest leaf allows.
  * Every candidate runs one untimed and three timed evaluations of the
@@ -373,6 +373,9 @@ fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p
  *                    lane per translation) or 4, the shared form, which
  *                    exists for FP64 at p = 6, 7 and FP32 at p = 9, 10 and
  *                    is their default.  Both forms give identical results.
+ *   chain_waves      waves sharing each M2M and L2L translation: 1 (one
+ *                    lane per translation) or 4 (the shared form, built and
+ *                    the default for p >= 5).  Identical results.
  * fmm_plan_set_tiles takes 0 in a field as "the default for this plan" and
  * rejects any other value the plan cannot use (FMM_EINVAL, plan unchanged).
  * fmm_plan_get_tiles writes the values evaluations use (host *tiles).
@@ -381,6 +384,7 @@ typedef struct fmm_tiles {
   int p2p_groups;
   int leaves_per_wave;
   int m2l_waves;
+  int chain_waves;
 } fmm_tiles;
 fmm_status fmm_plan_set_tiles(fmm_plan* plan, const fmm_tiles* tiles);
 fmm_status fmm_plan_get_tiles(const fmm_plan* plan, fmm_tiles* tiles);

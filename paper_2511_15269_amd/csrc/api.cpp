@@ -825,7 +825,8 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     void* fld = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = pl->profiling;
-    const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave, w0 = pl->m2l_waves;
+    const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave, w0 = pl->m2l_waves,
+              c0 = pl->chain_waves;
     auto cleanup = [&] {
       if (pot || fld) (void)hipStreamSynchronize(st);
       dev_free(pl, pot);
@@ -857,6 +858,13 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
         const float shared = time3();
         pl->m2l_waves = one < shared ? 1 : 0;
       }
+      if (pl->prm.p >= kChainShareMinOrder) {
+        pl->chain_waves = 1;
+        const float one = time3();
+        pl->chain_waves = 0;
+        const float shared = time3();
+        pl->chain_waves = one < shared ? 1 : 0;
+      }
       float best = -1.f;
       int bg = 0, bl = 0;
       for (int g : {1, 2, 4}) {
@@ -879,6 +887,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
       pl->p2p_groups = g0;
       pl->leaves_per_wave = l0;
       pl->m2l_waves = w0;
+      pl->chain_waves = c0;
       cleanup();
       throw;
     }
@@ -901,9 +910,14 @@ fmm_status fmm_plan_set_tiles(fmm_plan* pl, const fmm_tiles* t) {
                                                " for this order and precision"
                                          : std::string("m2l_waves must be 0 or 1 for this "
                                                        "order and precision")};
+    const int chain = pl->prm.p >= kChainShareMinOrder ? 4 : 1;
+    if (t->chain_waves != 0 && t->chain_waves != 1 && t->chain_waves != chain)
+      throw Error{FMM_EINVAL, chain > 1 ? std::string("chain_waves must be 0, 1 or 4")
+                                        : std::string("chain_waves must be 0 or 1 below p = 5")};
     pl->p2p_groups = t->p2p_groups;
     pl->leaves_per_wave = t->leaves_per_wave;
     pl->m2l_waves = t->m2l_waves == 1 ? 1 : 0;
+    pl->chain_waves = t->chain_waves == 1 ? 1 : 0;
   });
 }
 
@@ -913,6 +927,7 @@ fmm_status fmm_plan_get_tiles(const fmm_plan* pl, fmm_tiles* t) {
     t->p2p_groups = p2p_groups(pl);
     t->leaves_per_wave = leaves_per_wave(pl);
     t->m2l_waves = m2l_waves(pl);
+    t->chain_waves = chain_waves(pl);
   });
 }
 

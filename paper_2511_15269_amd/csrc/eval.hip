@@ -147,6 +147,105 @@ __global__ __launch_bounds__(64) void k_p2m(
   }
 }
 
+// ------------------------------------------- translations shared by waves
+// One translation (rotate, z-shift, rotate back) split over the NW waves of
+// a block, lane l of every wave working on the same translation.  The
+// rotations act degree by degree and the z-shift order by order, so wave w
+// rotates the degrees of share_mask(P, NW, w, false, kind) and z-shifts the
+// orders of share_mask(P, NW, w, true, kind), the coefficients passing
+// between the two through a 64-lane LDS tile (three barriers).  Every
+// coefficient undergoes the same operations in the same order as in
+// rotate_shift, so the results are identical to the one-lane form; each
+// wave holds a fraction of the coefficients and runs a fraction of the
+// chain of dependent operations, which raises the occupancy where the
+// one-lane form runs out of registers and cuts the latency of launches with
+// few translations (the level chains).
+
+// Multiply-adds of the two rotation phases on degree n (Y products and
+// azimuth steps) and of the z-shift of orders +-am (M2L: full blocks; M2M,
+// L2L: triangles).
+__host__ __device__ constexpr int rot_cost(int n) { return 4 * (n * n + n + 1) + 16 * n; }
+__host__ __device__ constexpr int shift_cost(int P, int am, int kind) {
+  const int d = P + 1 - am;
+  return (am > 0 ? 2 : 1) * (kind == kM2L ? d * d : d * (d + 1));
+}
+
+// Degrees (orders: false/true) of wave w: largest cost first, each onto the
+// least loaded wave (the first of equals).
+__host__ __device__ constexpr unsigned share_mask(int P, int NW, int w, bool orders, int kind) {
+  int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned done = 0;
+  for (int step = 0; step <= P; ++step) {
+    int pick = -1, pc = -1;
+    for (int x = 0; x <= P; ++x) {
+      if ((done >> x) & 1u) continue;
+      const int c = orders ? shift_cost(P, x, kind) : rot_cost(x);
+      if (c > pc) {
+        pc = c;
+        pick = x;
+      }
+    }
+    done |= 1u << pick;
+    int best = 0;
+    for (int j = 1; j < NW; ++j)
+      if (load[j] < load[best]) best = j;
+    load[best] += pc;
+    mask[best] |= 1u << pick;
+  }
+  return mask[w];
+}
+
+// coefficient loops over (n, m), k = cidx(n, m): the degrees of mask DM,
+// the orders of mask OM
+#define FMM_DEG_LOOP(DM, stmt)                        \
+  _Pragma("unroll") for (int n = 0; n <= P; ++n) {    \
+    if (!(((DM) >> n) & 1u)) continue;                \
+    _Pragma("unroll") for (int m = -n; m <= n; ++m) { \
+      const int k = cidx(n, m);                       \
+      stmt;                                           \
+    }                                                 \
+  }
+#define FMM_ORD_LOOP(OM, stmt)                                \
+  _Pragma("unroll") for (int n = 0; n <= P; ++n) {            \
+    _Pragma("unroll") for (int m = -n; m <= n; ++m) {         \
+      if (!(((OM) >> (m < 0 ? -m : m)) & 1u)) continue;       \
+      const int k = cidx(n, m);                               \
+      stmt;                                                   \
+    }                                                         \
+  }
+
+// Wave W's part of one translation per lane: v holds the wave's degrees on
+// entry and the translated coefficients of those degrees on return.  All
+// waves of the block call it together (barriers inside; lanes with act
+// false take no part but reach them).  X: LDS tile of (K - 1) kRow + 64
+// entries, free again on return.
+template <int P, int KIND, typename T, int NW, int W>
+__device__ __forceinline__ void turn_shared(T* v, bool act, const Turn<P, KIND, T>& g,
+                                            const T* __restrict__ tab, T* X, int lane) {
+  constexpr int K = K_<P>::value;
+  constexpr unsigned DM = share_mask(P, NW, W, false, KIND);
+  constexpr unsigned OM = share_mask(P, NW, W, true, KIND);
+  if (act) {
+    turn_forward<P, KIND, T, DM>(v, g, tab);
+    FMM_DEG_LOOP(DM, X[k * kRow + lane] = v[k])
+  }
+  __syncthreads();
+  if (act) {
+    T z[K];
+    FMM_ORD_LOOP(OM, z[k] = X[k * kRow + lane])
+    zshift<P, KIND, T, OM>(z, g.a, g.b, tab);
+    FMM_ORD_LOOP(OM, X[k * kRow + lane] = z[k])
+  }
+  __syncthreads();
+  if (act) FMM_DEG_LOOP(DM, v[k] = X[k * kRow + lane])
+  __syncthreads();
+  if (act) turn_back<P, KIND, T, DM>(v, g, tab);
+}
+
+// Waves per translation of the shared forms.
+constexpr int kShareWaves = 4;
+
 // ---------------------------------------------------------------- M2M
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_m2m(
@@ -173,6 +272,46 @@ __global__ __launch_bounds__(64) void k_m2m(
   if (live && (i & (nch - 1)) == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) C[pa * K + k] = v[k];
+  }
+}
+
+// k_m2m with each translation shared by the kShareWaves waves of a block
+// (turn_shared); the same results.
+template <int P, typename T, int W>
+__device__ __forceinline__ void m2m_wave(int lane, int64_t i, bool live, int64_t c, int64_t pa,
+                                         int s, const Turn<P, kM2M, T>& g,
+                                         const T* __restrict__ tab, T* C, T* X) {
+  constexpr int K = K_<P>::value;
+  constexpr unsigned DM = share_mask(P, kShareWaves, W, false, kM2M);
+  T v[K];
+  FMM_DEG_LOOP(DM, v[k] = live ? C[c * K + k] : T(0))
+  turn_shared<P, kM2M, T, kShareWaves, W>(v, true, g, tab, X, lane);
+  const int nch = 1 << s;
+  for (int off = 1; off < nch; off <<= 1) FMM_DEG_LOOP(DM, v[k] += __shfl_xor(v[k], off, 64))
+  if (live && (i & (nch - 1)) == 0) FMM_DEG_LOOP(DM, C[pa * K + k] = v[k])
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(64 * kShareWaves) void k_m2m_shared(
+    int64_t nchild, const int32_t* __restrict__ par, const int32_t* __restrict__ child0,
+    int s, const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ tab, T* C) {
+  constexpr int K = K_<P>::value;
+  __shared__ T X[(K - 1) * kRow + 64];
+  const int lane = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = i < nchild;
+  const int64_t ii = live ? i : 0;
+  const int64_t c = child0[ii >> s] + (ii & ((1 << s) - 1));
+  const int64_t pa = par[ii >> s];
+  const Turn<P, kM2M, T> g(cx[c] - cx[pa], cy[c] - cy[pa], cz[c] - cz[pa], scale[c], scale[pa]);
+  switch (w) {
+    case 0: m2m_wave<P, T, 0>(lane, i, live, c, pa, s, g, tab, C, X); break;
+    case 1: m2m_wave<P, T, 1>(lane, i, live, c, pa, s, g, tab, C, X); break;
+    case 2: m2m_wave<P, T, 2>(lane, i, live, c, pa, s, g, tab, C, X); break;
+    default: m2m_wave<P, T, 3>(lane, i, live, c, pa, s, g, tab, C, X); break;
   }
 }
 
@@ -278,50 +417,6 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(
   }
 }
 
-// The same M2L items with the translation of each item shared by the NW
-// waves of a block: lane l of every wave works on item l.  The rotations
-// act degree by degree and the z-shift order by order, so wave w rotates
-// the degrees of share_mask(P, NW, w, false) and z-shifts the orders of
-// share_mask(P, NW, w, true), the coefficients passing between the two
-// through a 64-lane LDS tile (three barriers per translation).  Every
-// coefficient undergoes the same operations in the same order as in k_m2l,
-// so the two kernels give identical results; the waves of the shared form
-// hold a fraction of the coefficients each, which lets more of them share a
-// SIMD and shortens each wave's chain of dependent operations.
-
-// Multiply-adds of the two rotation phases on degree n (Y products and
-// azimuth steps) and of the M2L z-shift of orders +-am.
-__host__ __device__ constexpr int rot_cost(int n) { return 4 * (n * n + n + 1) + 16 * n; }
-__host__ __device__ constexpr int shift_cost(int P, int am) {
-  return (am > 0 ? 2 : 1) * (P + 1 - am) * (P + 1 - am);
-}
-
-// Degrees (orders: false/true) of wave w: largest cost first, each onto the
-// least loaded wave (the first of equals).
-__host__ __device__ constexpr unsigned share_mask(int P, int NW, int w, bool orders) {
-  int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  unsigned mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  unsigned done = 0;
-  for (int step = 0; step <= P; ++step) {
-    int pick = -1, pc = -1;
-    for (int x = 0; x <= P; ++x) {
-      if ((done >> x) & 1u) continue;
-      const int c = orders ? shift_cost(P, x) : rot_cost(x);
-      if (c > pc) {
-        pc = c;
-        pick = x;
-      }
-    }
-    done |= 1u << pick;
-    int best = 0;
-    for (int j = 1; j < NW; ++j)
-      if (load[j] < load[best]) best = j;
-    load[best] += pc;
-    mask[best] |= 1u << pick;
-  }
-  return mask[w];
-}
-
 template <int P, typename T, int NW, int W>
 __device__ __forceinline__ void m2l_share(int lane, int jb, int je, int iters, double tx,
                                           double ty, double tz, double rt,
@@ -333,65 +428,29 @@ __device__ __forceinline__ void m2l_share(int lane, int jb, int je, int iters, d
                                           const T* __restrict__ C, const T* __restrict__ tab,
                                           T* X) {
   constexpr int K = K_<P>::value;
-  constexpr unsigned DM = share_mask(P, NW, W, false);
-  constexpr unsigned OM = share_mask(P, NW, W, true);
-  // coefficient loops over (n, m): k = cidx(n, m) of the wave's degrees
-  // (DM) or orders (OM)
-#define FMM_DEG_LOOP(stmt)                                  \
-  _Pragma("unroll") for (int n = 0; n <= P; ++n) {          \
-    if (!((DM >> n) & 1u)) continue;                        \
-    _Pragma("unroll") for (int m = -n; m <= n; ++m) {       \
-      const int k = cidx(n, m);                             \
-      stmt;                                                 \
-    }                                                       \
-  }
-#define FMM_ORD_LOOP(stmt)                                  \
-  _Pragma("unroll") for (int n = 0; n <= P; ++n) {          \
-    _Pragma("unroll") for (int m = -n; m <= n; ++m) {       \
-      if (!((OM >> (m < 0 ? -m : m)) & 1u)) continue;       \
-      const int k = cidx(n, m);                             \
-      stmt;                                                 \
-    }                                                       \
-  }
+  constexpr unsigned DM = share_mask(P, NW, W, false, kM2L);
   T acc[K];
-  FMM_DEG_LOOP(acc[k] = T(0))
+  FMM_DEG_LOOP(DM, acc[k] = T(0))
   for (int it = 0; it < iters; ++it) {
     const int j = jb + it;
     const bool act = j < je;
     const int sidx = act ? src[j] : 0;
     const Turn<P, kM2L, T> g(cx[sidx] - tx, cy[sidx] - ty, cz[sidx] - tz, scale[sidx], rt);
     T v[K];
+    if (act) FMM_DEG_LOOP(DM, v[k] = C[(int64_t)sidx * K + k])
+    turn_shared<P, kM2L, T, NW, W>(v, act, g, tab, X, lane);
     if (act) {
-      FMM_DEG_LOOP(v[k] = C[(int64_t)sidx * K + k])
-      turn_forward<P, kM2L, T, DM>(v, g, tab);
-      FMM_DEG_LOOP(X[k * kRow + lane] = v[k])
-    }
-    __syncthreads();
-    if (act) {
-      T z[K];
-      FMM_ORD_LOOP(z[k] = X[k * kRow + lane])
-      zshift<P, kM2L, T, OM>(z, g.a, g.b, tab);
-      FMM_ORD_LOOP(X[k * kRow + lane] = z[k])
-    }
-    __syncthreads();
-    if (act) {
-      FMM_DEG_LOOP(v[k] = X[k * kRow + lane])
-    }
-    __syncthreads();
-    if (act) {
-      turn_back<P, kM2L, T, DM>(v, g, tab);
-      {
-        // a plain add, as in k_m2l
+      // a plain add, as in k_m2l
 #pragma clang fp contract(off)
-        FMM_DEG_LOOP(acc[k] += v[k])
-      }
+      FMM_DEG_LOOP(DM, acc[k] += v[k])
     }
   }
-  FMM_DEG_LOOP(X[k * kRow + lane] = acc[k])
-#undef FMM_DEG_LOOP
-#undef FMM_ORD_LOOP
+  FMM_DEG_LOOP(DM, X[k * kRow + lane] = acc[k])
 }
 
+// The same M2L items with the translation of each item shared by the NW
+// waves of a block (turn_shared): lane l of every wave works on item l.
+// Gives the same results as k_m2l.
 template <int P, typename T, int NW>
 __global__ __launch_bounds__(kM2LBlock * NW) void k_m2l_shared(
     int64_t nblocks, const int32_t* __restrict__ item_tgt,
@@ -475,6 +534,52 @@ __global__ __launch_bounds__(64) void k_l2l_fin(
     const bool own = fin_own[g] != 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) out[t * K + k] = (own ? D[t * K + k] : T(0)) + v[k];
+  }
+}
+
+// k_l2l_fin with each translation shared by the kShareWaves waves of a
+// block (turn_shared) and the group size gs a launch argument; the same
+// results.
+template <int P, typename T, int W>
+__device__ __forceinline__ void l2l_fin_wave(int lane, bool live, int j, int gs, int64_t t,
+                                             int64_t a, bool own, const Turn<P, kL2L, T>& g,
+                                             const T* __restrict__ tab, const T* src,
+                                             const T* __restrict__ D, T* out, T* X) {
+  constexpr int K = K_<P>::value;
+  constexpr unsigned DM = share_mask(P, kShareWaves, W, false, kL2L);
+  const bool act = a >= 0;
+  T v[K];
+  FMM_DEG_LOOP(DM, v[k] = act ? src[a * K + k] : T(0))
+  turn_shared<P, kL2L, T, kShareWaves, W>(v, act, g, tab, X, lane);
+  for (int off = 1; off < gs; off <<= 1) FMM_DEG_LOOP(DM, v[k] += __shfl_xor(v[k], off, 64))
+  if (live && j == 0) FMM_DEG_LOOP(DM, out[t * K + k] = (own ? D[t * K + k] : T(0)) + v[k])
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(64 * kShareWaves) void k_l2l_fin_shared(
+    int64_t nfin, int gs, const int32_t* __restrict__ fin_box,
+    const int32_t* __restrict__ fin_own, const int32_t* __restrict__ fin_anc,
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const T* __restrict__ tab, const T* src, const T* __restrict__ D, T* out) {
+  constexpr int K = K_<P>::value;
+  __shared__ T X[(K - 1) * kRow + 64];
+  const int lane = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t g = i / gs;
+  const int j = (int)(i % gs);
+  const bool live = g < nfin;
+  const int64_t t = live ? fin_box[g] : 0;
+  const int64_t a = live ? fin_anc[i] : -1;
+  const bool own = live && fin_own[g] != 0;
+  const int64_t aa = a >= 0 ? a : t;  // a valid pair for lanes without a source
+  const Turn<P, kL2L, T> tr(cx[aa] - cx[t], cy[aa] - cy[t], cz[aa] - cz[t], scale[aa], scale[t]);
+  switch (w) {
+    case 0: l2l_fin_wave<P, T, 0>(lane, live, j, gs, t, a, own, tr, tab, src, D, out, X); break;
+    case 1: l2l_fin_wave<P, T, 1>(lane, live, j, gs, t, a, own, tr, tab, src, D, out, X); break;
+    case 2: l2l_fin_wave<P, T, 2>(lane, live, j, gs, t, a, own, tr, tab, src, D, out, X); break;
+    default: l2l_fin_wave<P, T, 3>(lane, live, j, gs, t, a, own, tr, tab, src, D, out, X); break;
   }
 }
 
@@ -773,8 +878,16 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   else p2m(k_p2m<P, T, 8>);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
+  const bool chain_shared = P >= kChainShareMinOrder && chain_waves(pl) > 1;
   for (const Step& S : SS.m2m_steps) {
     const int64_t nchild = S.n << s;
+    if constexpr (P >= kChainShareMinOrder) {
+      if (chain_shared) {
+        k_m2m_shared<P, T><<<blocks(nchild, 64), 64 * kShareWaves, 0, st>>>(
+            nchild, S.a, S.b, s, pl->cx, pl->cy, pl->cz, pl->scale, tab, C);
+        continue;
+      }
+    }
     k_m2m<P, T><<<blocks(nchild, 64), 64, 0, st>>>(nchild, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
                                                    pl->scale, tab, C);
   }
@@ -805,6 +918,14 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
     const FinList& F = Ls.fin[k];
     if (F.n == 0) continue;
     const T* from = k == 0 ? D : Dfin;
+    if constexpr (P >= kChainShareMinOrder) {
+      if (chain_shared) {
+        k_l2l_fin_shared<P, T><<<blocks(F.n * F.gs, 64), 64 * kShareWaves, 0, st>>>(
+            F.n, F.gs, F.box, F.own, F.anc, pl->cx, pl->cy, pl->cz, pl->scale, tab, from, D,
+            Dfin);
+        continue;
+      }
+    }
     auto l2l = [&](auto kern) {
       kern<<<blocks(F.n * F.gs, 64), 64, 0, st>>>(F.n, F.box, F.own, F.anc, pl->cx, pl->cy,
                                                  pl->cz, pl->scale, tab, from, D, Dfin);
@@ -879,6 +1000,9 @@ int p2p_groups(const fmm_plan* pl) {
   if (pl->p2p_groups && valid_p2p_groups(pl, pl->p2p_groups)) return pl->p2p_groups;
   const int m = pl->max_leaf_count;
   return m > 32 ? 1 : (m > 16 ? 2 : 4);
+}
+int chain_waves(const fmm_plan* pl) {
+  return pl->prm.p < kChainShareMinOrder || pl->chain_waves == 1 ? 1 : kShareWaves;
 }
 int m2l_waves(const fmm_plan* pl) {
   const int shared = m2l_share_waves(pl->prm.p, pl->prm.precision == FMM_FP64);

@@ -195,6 +195,9 @@ struct fmm_plan {
   // 1: one lane per M2L translation; 0: the shared form where it is built
   // (m2l_share_waves), else one lane
   int m2l_waves = 0;
+  // 1: one lane per M2M / L2L translation; 0: shared by four waves from
+  // order kChainShareMinOrder on
+  int chain_waves = 0;
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   int nsides = 1;               // 2: separate sources (side 0) and targets (side 1)
   fmm::Side side[2];
@@ -326,6 +329,9 @@ void direct_sum(int64_t n, const double* pos, const void* q, int precision,
 int p2p_groups(const fmm_plan* pl);
 int leaves_per_wave(const fmm_plan* pl);
 int m2l_waves(const fmm_plan* pl);
+int chain_waves(const fmm_plan* pl);
+// lowest order with the shared M2M / L2L forms
+constexpr int kChainShareMinOrder = 5;
 // Waves per translation of the shared M2L form for order p and precision
 // (1: no shared form).  It is built where it was measured faster than one
 // lane per translation: FP64 at p = 6, 7 (above, its LDS tile caps the

@@ -543,12 +543,41 @@ def test_m2l_shared_form_is_identical_to_one_lane_form(fmm, prec, p, n, leaf, s,
     assert plan.tiles()["m2l_waves"] == 1
 
 
+@pytest.mark.parametrize("prec,p,n,leaf,s,theta", [
+    ("fp64", 5, 30000, 16, 1, 0.6), ("fp64", 8, 40000, 64, 3, 0.8), ("fp64", 10, 30000, 32, 2, 0.5),
+    ("fp32", 6, 40000, 24, 2, 0.7), ("fp32", 9, 30000, 64, 3, 0.6)])
+def test_chain_shared_form_is_identical_to_one_lane_form(fmm, prec, p, n, leaf, s, theta):
+    """M2M and L2L translations shared by four waves give the same bits as
+    one lane per translation, forward and transposed (s = 1, 2, 3 cover
+    child groups of 2, 4 and 8 lanes; deep trees give long ancestor
+    groups in the L2L lists)."""
+    _say(f"[chain forms] {prec} p={p} n={n} leaf={leaf} s={s} theta={theta}")
+    pos, q = workloads.clustered(n, 40 + p)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda().to(dt)
+    plan = fmm.Plan(pt, p=p, leaf_max=leaf, splits=s, theta=theta, precision=prec)
+    assert plan.tiles()["chain_waves"] == 4
+    u1, f1 = plan.evaluate(qt)
+    t1 = plan.evaluate_transposed(qt)
+    plan.set_tiles(chain_waves=1)
+    assert plan.tiles()["chain_waves"] == 1
+    u0, f0 = plan.evaluate(qt)
+    t0 = plan.evaluate_transposed(qt)
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1) and torch.equal(f0, f1)
+    assert torch.equal(t0[0], t1[0]) and torch.equal(t0[1], t1[1])
+    with pytest.raises(fmm.FMMError):
+        plan.set_tiles(chain_waves=2)
+
+
 def test_m2l_one_lane_form_where_no_shared_form_is_built(fmm):
     pos, _ = workloads.uniform_cube(5000, 3)
     pt = torch.from_numpy(pos).cuda()
     for prec, p in (("fp64", 8), ("fp64", 5), ("fp32", 8)):
         plan = fmm.Plan(pt, p=p, leaf_max=64, splits=3, theta=0.7, precision=prec)
         assert plan.tiles()["m2l_waves"] == 1
+        assert plan.tiles()["chain_waves"] == 4
         with pytest.raises(fmm.FMMError):
             plan.set_tiles(m2l_waves=4)
         plan.set_tiles(m2l_waves=1)

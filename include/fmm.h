@@ -348,18 +348,20 @@ fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
                                  int64_t* passes);
 
 /* Choose the launch tiles of the single-vector evaluation (fmm_tiles) by
- * timing them on this plan: first the M2L form and the M2M / L2L form (one
- * lane or several waves per translation), then the number of source groups of the near-field
- * kernel (1, 2 or 4) together with the number of leaves per wave of P2M and
- * L2P (1, 2, 4 or 8), among the values the plan's largest leaf allows.
- * Every candidate runs one untimed and three timed evaluations of the
- * charges q (device, [n], the plan's precision) on `stream`; the fastest
- * values are stored in the plan and used by every later evaluation
- * (results change only by the summation order inside the near field and
- * the multipole sums).  The chosen groups and leaves per wave are written
- * to *p2p_groups and *leaves_per_wave (host; may be NULL); all three values
- * can be read with fmm_plan_get_tiles.  Synchronises `stream`; allocates and frees temporary output
- * buffers.  Errors: FMM_EINVAL (NULL plan or q), FMM_ENOMEM, FMM_EDEVICE. */
+ * timing them on this plan: first the M2L form, the M2M / L2L form (one
+ * lane or several waves per translation) and the near field's stream, then
+ * the number of source groups of the near-field kernel (1, 2 or 4) together
+ * with the number of leaves per wave of P2M and L2P (1, 2, 4 or 8), among
+ * the values the plan's largest leaf allows.  Every candidate runs one
+ * untimed and three timed evaluations of the charges q (device, [n], the
+ * plan's precision) on `stream`; the fastest values are stored in the plan
+ * and used by every later evaluation (results change only by the summation
+ * order inside the near field and the multipole sums).  The chosen groups
+ * and leaves per wave are written to *p2p_groups and *leaves_per_wave
+ * (host; may be NULL); every chosen value can be read with
+ * fmm_plan_get_tiles.  Synchronises `stream`; allocates and frees
+ * temporary output buffers.  Errors: FMM_EINVAL (NULL plan or q),
+ * FMM_ENOMEM, FMM_EDEVICE. */
 fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p2p_groups,
                              int* leaves_per_wave);
 
@@ -376,6 +378,12 @@ fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p
  *   chain_waves      waves sharing each M2M and L2L translation: 1 (one
  *                    lane per translation) or 4 (the shared form, built and
  *                    the default for p >= 5).  Identical results.
+ *   near_stream      2 (default): the near field runs on a second stream
+ *                    of the plan beside the far-field chain (M2M, M2L,
+ *                    L2L), forked after P2M and joined before L2P; 1: every
+ *                    stage on the caller's stream.  Identical results.
+ *                    While stage profiling is on, stages run one after
+ *                    another on the caller's stream.
  * fmm_plan_set_tiles takes 0 in a field as "the default for this plan" and
  * rejects any other value the plan cannot use (FMM_EINVAL, plan unchanged).
  * fmm_plan_get_tiles writes the values evaluations use (host *tiles).
@@ -385,6 +393,7 @@ typedef struct fmm_tiles {
   int leaves_per_wave;
   int m2l_waves;
   int chain_waves;
+  int near_stream;
 } fmm_tiles;
 fmm_status fmm_plan_set_tiles(fmm_plan* plan, const fmm_tiles* tiles);
 fmm_status fmm_plan_get_tiles(const fmm_plan* plan, fmm_tiles* tiles);

@@ -328,12 +328,13 @@ class Plan:
         t = FmmTiles()
         check(lib().fmm_plan_get_tiles(self._h, ctypes.byref(t)))
         return {"p2p_groups": t.p2p_groups, "leaves_per_wave": t.leaves_per_wave,
-                "m2l_waves": t.m2l_waves, "chain_waves": t.chain_waves}
+                "m2l_waves": t.m2l_waves, "chain_waves": t.chain_waves,
+                "near_stream": t.near_stream}
 
     def set_tiles(self, p2p_groups: int = 0, leaves_per_wave: int = 0,
-                  m2l_waves: int = 0, chain_waves: int = 0) -> None:
+                  m2l_waves: int = 0, chain_waves: int = 0, near_stream: int = 0) -> None:
         """Set the launch tiles (0: the plan's default; fmm_plan_set_tiles)."""
-        t = FmmTiles(p2p_groups, leaves_per_wave, m2l_waves, chain_waves)
+        t = FmmTiles(p2p_groups, leaves_per_wave, m2l_waves, chain_waves, near_stream)
         check(lib().fmm_plan_set_tiles(self._h, ctypes.byref(t)))
 
     def set_profiling(self, on: bool = True) -> None:

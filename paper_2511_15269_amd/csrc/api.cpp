@@ -109,6 +109,19 @@ void plan_free_all(fmm_plan* pl) {
   for (auto& b : pl->bufs) dev_free(pl, b.ptr);
   pl->bufs.clear();
   pl->device_bytes = 0;
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
+  pl->ev_fork = pl->ev_join = nullptr;
+  pl->side_stream = nullptr;
+}
+
+// The evaluation's second stream and its fork / join events (on the
+// plan's device, which is current during creation).
+void make_fork(fmm_plan* pl) {
+  FMM_HIP(hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking));
+  FMM_HIP(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+  FMM_HIP(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
 }
 
 void make_steps(fmm_plan* pl, const std::vector<std::vector<TreeDesc>>& groups,
@@ -436,6 +449,7 @@ fmm_status fmm_plan_create_ex(const double* pos, int64_t n, const fmm_params* pr
       build_structure(pl.get(), pos, n, prm, st);
       make_steps(pl.get(), {{TreeDesc{pl->L, pl->level_off, 0, 0}}}, st);
       alloc_workspace(pl.get(), st);
+      make_fork(pl.get());
     } catch (...) {
       (void)hipStreamSynchronize(st);
       plan_free_all(pl.get());
@@ -494,6 +508,7 @@ fmm_status fmm_multi_plan_create_ex(const double* pos, const int64_t* offsets, i
       (void)hipStreamSynchronize(st);
       free_subs();
       alloc_workspace(pl.get(), st);
+      make_fork(pl.get());
     } catch (...) {
       (void)hipStreamSynchronize(st);
       free_subs();
@@ -551,6 +566,7 @@ fmm_status fmm_plan_create_st(const double* src, int64_t ns, const double* tgt, 
       (void)hipStreamSynchronize(st);
       free_subs();
       alloc_workspace(pl.get(), st);
+      make_fork(pl.get());
     } catch (...) {
       (void)hipStreamSynchronize(st);
       free_subs();
@@ -826,7 +842,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = pl->profiling;
     const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave, w0 = pl->m2l_waves,
-              c0 = pl->chain_waves;
+              c0 = pl->chain_waves, s0 = pl->near_stream;
     auto cleanup = [&] {
       if (pot || fld) (void)hipStreamSynchronize(st);
       dev_free(pl, pot);
@@ -865,6 +881,13 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
         const float shared = time3();
         pl->chain_waves = one < shared ? 1 : 0;
       }
+      {
+        pl->near_stream = 1;
+        const float one = time3();
+        pl->near_stream = 0;
+        const float two = time3();
+        pl->near_stream = one < two ? 1 : 0;
+      }
       float best = -1.f;
       int bg = 0, bl = 0;
       for (int g : {1, 2, 4}) {
@@ -888,6 +911,7 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
       pl->leaves_per_wave = l0;
       pl->m2l_waves = w0;
       pl->chain_waves = c0;
+      pl->near_stream = s0;
       cleanup();
       throw;
     }
@@ -916,8 +940,11 @@ fmm_status fmm_plan_set_tiles(fmm_plan* pl, const fmm_tiles* t) {
                                         : std::string("chain_waves must be 0 or 1 below p = 5")};
     pl->p2p_groups = t->p2p_groups;
     pl->leaves_per_wave = t->leaves_per_wave;
+    if (t->near_stream != 0 && t->near_stream != 1 && t->near_stream != 2)
+      throw Error{FMM_EINVAL, "near_stream must be 0, 1 or 2"};
     pl->m2l_waves = t->m2l_waves == 1 ? 1 : 0;
     pl->chain_waves = t->chain_waves == 1 ? 1 : 0;
+    pl->near_stream = t->near_stream == 1 ? 1 : 0;
   });
 }
 
@@ -928,6 +955,7 @@ fmm_status fmm_plan_get_tiles(const fmm_plan* pl, fmm_tiles* t) {
     t->leaves_per_wave = leaves_per_wave(pl);
     t->m2l_waves = m2l_waves(pl);
     t->chain_waves = chain_waves(pl);
+    t->near_stream = pl->near_stream == 1 ? 1 : 2;
   });
 }
 

@@ -840,10 +840,43 @@ __global__ void k_adjoint_combine(int64_t n, const T* __restrict__ q, const T* _
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// One evaluation, every stage on the caller's stream: P2P writes the near
-// field in leaf order, L2P adds the far field and writes the outputs.  (Running P2P concurrently on a second
-// stream does not pay: it fills the GPU and delays the small level-by-level
-// launches of the far field by as much as it hides.)
+// The near field (P2P) over the direct lists Ls into near, on stream sp:
+// one launch over the work items, then the partial sums of the leaves whose
+// list was split.
+template <typename T>
+void near_field(fmm_plan* pl, const ListSet& Ls, const Src<T>* src, int64_t n, T* near,
+                bool field, hipStream_t sp, const StageMarks& mk) {
+  mk.begin(kStP2P, sp);
+  const int G = p2p_groups(pl);
+  auto p2p = [&](auto kern) {
+    kern<<<(unsigned)Ls.n_pitems, 64, 0, sp>>>(n, Ls.pitem_leaf, Ls.pitem_kb, Ls.pitem_ke,
+                                               Ls.pitem_out, pl->leaf_start, pl->xs, pl->ys,
+                                               pl->zs, src, Ls.p2p_src, pl->has_dup ? 1 : 0, near,
+                                               (T*)Ls.p2p_part);
+  };
+  if (field) {
+    if (G == 1) p2p(k_p2p<T, true, 1>);
+    else if (G == 2) p2p(k_p2p<T, true, 2>);
+    else p2p(k_p2p<T, true, 4>);
+  } else {
+    if (G == 1) p2p(k_p2p<T, false, 1>);
+    else if (G == 2) p2p(k_p2p<T, false, 2>);
+    else p2p(k_p2p<T, false, 4>);
+  }
+  if (Ls.n_psplit > 0) {
+    auto sum = [&](auto kern) {
+      kern<<<(unsigned)Ls.n_psplit, 64, 0, sp>>>(n, Ls.psplit_leaf, Ls.psplit_first,
+                                                 Ls.psplit_cnt, Ls.pitem_out, pl->leaf_start,
+                                                 (const T*)Ls.p2p_part, near);
+    };
+    if (field) sum(k_p2p_sum<T, true>);
+    else sum(k_p2p_sum<T, false>);
+  }
+  mk.end(kStP2P, sp);
+}
+
+// One evaluation: P2P writes the near field in leaf order, L2P adds the far
+// field and writes the outputs.
 template <int P, typename T>
 void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* field,
          hipStream_t st) {
@@ -877,6 +910,18 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   else if (GL == 4) p2m(k_p2m<P, T, 4>);
   else p2m(k_p2m<P, T, 8>);
   mk.end(kStP2M, st);
+  // The near field needs only the leaf-ordered source records of P2M: it
+  // runs on the plan's second stream beside the far-field chain (M2M, M2L,
+  // L2L), so each fills the other's idle issue slots; L2P joins the two.
+  // Stage profiling keeps the stages one after another on st.
+  const bool fork = pl->side_stream != nullptr && !pl->profiling && pl->near_stream != 1;
+  const hipStream_t sp = fork ? pl->side_stream : st;
+  if (fork) {
+    FMM_HIP(hipEventRecord(pl->ev_fork, st));
+    FMM_HIP(hipStreamWaitEvent(sp, pl->ev_fork, 0));
+  }
+  near_field<T>(pl, Ls, src, n, near, field != nullptr, sp, mk);
+  if (fork) FMM_HIP(hipEventRecord(pl->ev_join, sp));
   mk.begin(kStM2M, st);
   const bool chain_shared = P >= kChainShareMinOrder && chain_waves(pl) > 1;
   for (const Step& S : SS.m2m_steps) {
@@ -939,34 +984,7 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
     }
   }
   mk.end(kStL2L, st);
-  // near field
-  mk.begin(kStP2P, st);
-  const int G = p2p_groups(pl);
-  auto p2p = [&](auto kern) {
-    kern<<<(unsigned)Ls.n_pitems, 64, 0, st>>>(n, Ls.pitem_leaf, Ls.pitem_kb, Ls.pitem_ke,
-                                               Ls.pitem_out, pl->leaf_start, pl->xs, pl->ys,
-                                               pl->zs, src, Ls.p2p_src, pl->has_dup ? 1 : 0, near,
-                                               (T*)Ls.p2p_part);
-  };
-  if (field) {
-    if (G == 1) p2p(k_p2p<T, true, 1>);
-    else if (G == 2) p2p(k_p2p<T, true, 2>);
-    else p2p(k_p2p<T, true, 4>);
-  } else {
-    if (G == 1) p2p(k_p2p<T, false, 1>);
-    else if (G == 2) p2p(k_p2p<T, false, 2>);
-    else p2p(k_p2p<T, false, 4>);
-  }
-  if (Ls.n_psplit > 0) {
-    auto sum = [&](auto kern) {
-      kern<<<(unsigned)Ls.n_psplit, 64, 0, st>>>(n, Ls.psplit_leaf, Ls.psplit_first,
-                                                 Ls.psplit_cnt, Ls.pitem_out, pl->leaf_start,
-                                                 (const T*)Ls.p2p_part, near);
-    };
-    if (field) sum(k_p2p_sum<T, true>);
-    else sum(k_p2p_sum<T, false>);
-  }
-  mk.end(kStP2P, st);
+  if (fork) FMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
   mk.begin(kStL2P, st);
   auto l2p = [&](auto kern) {
     kern<<<(unsigned)((nlt + GL - 1) / GL), 64, 0, st>>>(

@@ -198,6 +198,9 @@ struct fmm_plan {
   // 1: one lane per M2M / L2L translation; 0: shared by four waves from
   // order kChainShareMinOrder on
   int chain_waves = 0;
+  // 1: the near field on the caller's stream after the far-field chain; 0:
+  // on the plan's second stream beside it
+  int near_stream = 0;
   int32_t* leaf_box = nullptr;  // [nleaf] global box id of each leaf
   int nsides = 1;               // 2: separate sources (side 0) and targets (side 1)
   fmm::Side side[2];
@@ -225,6 +228,12 @@ struct fmm_plan {
   // temporaries during the build; stream passed to the callbacks
   fmm_allocator allocator{nullptr, nullptr, nullptr};
   hipStream_t alloc_stream = nullptr;
+
+  // second stream of the evaluation: the near field runs on it beside the
+  // far-field chain (forked after P2M, joined before L2P; events without
+  // timing; default priority)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // stage timing (fmm_plan_set_profiling)
   bool profiling = false;

@@ -382,8 +382,9 @@ fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p
  *                    of the plan beside the far-field chain (M2M, M2L,
  *                    L2L), forked after P2M and joined before L2P; 1: every
  *                    stage on the caller's stream.  Identical results.
- *                    While stage profiling is on, stages run one after
- *                    another on the caller's stream.
+ *                    While stage profiling is on, and inside graphs
+ *                    (fmm_graph_create), stages run one after another on
+ *                    one stream.
  * fmm_plan_set_tiles takes 0 in a field as "the default for this plan" and
  * rejects any other value the plan cannot use (FMM_EINVAL, plan unchanged).
  * fmm_plan_get_tiles writes the values evaluations use (host *tiles).
@@ -411,7 +412,8 @@ fmm_status fmm_plan_destroy(fmm_plan* plan);
  *          addresses: each replay reads q's current contents and rewrites
  *          pot (and field).
  *   out    host, receives the graph (free with fmm_graph_destroy).
- * Nothing runs at creation.  The graph contains kernel launches only.
+ * Nothing runs at creation.  The graph contains kernel launches only, in
+ * one sequence (no second branch for the near field).
  * Errors: as fmm_evaluate, FMM_EDEVICE if capture or instantiation fails. */
 typedef struct fmm_graph fmm_graph;
 fmm_status fmm_graph_create(fmm_plan* plan, int transposed, const void* q, int nrhs,

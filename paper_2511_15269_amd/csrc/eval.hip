@@ -916,12 +916,15 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
   // Stage profiling keeps the stages one after another on st.
   const bool fork = pl->side_stream != nullptr && !pl->profiling && pl->near_stream != 1;
   const hipStream_t sp = fork ? pl->side_stream : st;
-  if (fork) {
-    FMM_HIP(hipEventRecord(pl->ev_fork, st));
-    FMM_HIP(hipStreamWaitEvent(sp, pl->ev_fork, 0));
-  }
-  near_field<T>(pl, Ls, src, n, near, field != nullptr, sp, mk);
-  if (fork) FMM_HIP(hipEventRecord(pl->ev_join, sp));
+  if (fork) FMM_HIP(hipEventRecord(pl->ev_fork, st));
+  auto near_part = [&] {
+    if (fork) FMM_HIP(hipStreamWaitEvent(sp, pl->ev_fork, 0));
+    near_field<T>(pl, Ls, src, n, near, field != nullptr, sp, mk);
+    if (fork) FMM_HIP(hipEventRecord(pl->ev_join, sp));
+  };
+  // enqueued after the far-field chain when forked, so that the chain's
+  // small level launches are not queued behind the near field's blocks
+  if (!fork) near_part();
   mk.begin(kStM2M, st);
   const bool chain_shared = P >= kChainShareMinOrder && chain_waves(pl) > 1;
   for (const Step& S : SS.m2m_steps) {
@@ -984,7 +987,10 @@ void run(fmm_plan* pl, const Workspace& ws, int dir, const T* q, T* pot, T* fiel
     }
   }
   mk.end(kStL2L, st);
-  if (fork) FMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
+  if (fork) {
+    near_part();
+    FMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
+  }
   mk.begin(kStL2P, st);
   auto l2p = [&](auto kern) {
     kern<<<(unsigned)((nlt + GL - 1) / GL), 64, 0, st>>>(

@@ -571,6 +571,43 @@ def test_chain_shared_form_is_identical_to_one_lane_form(fmm, prec, p, n, leaf, 
         plan.set_tiles(chain_waves=2)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_near_field_stream_choice_gives_identical_results(fmm, prec):
+    """The near field on the plan's second stream (default) and on the
+    caller's stream give the same bits, forward, transposed and in a graph
+    replayed after eager passes on another stream."""
+    _say(f"[near stream] {prec}")
+    pos, q = workloads.uniform_cube(60000, 23)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda().to(dt)
+    plan = fmm.Plan(pt, p=7, leaf_max=32, splits=3, theta=0.7, precision=prec)
+    assert plan.tiles()["near_stream"] == 2
+    u2, f2 = plan.evaluate(qt)
+    t2 = plan.evaluate_transposed(qt)
+    g = fmm.Graph(plan, qt, field=True)
+    plan.set_tiles(near_stream=1)
+    assert plan.tiles()["near_stream"] == 1
+    u1, f1 = plan.evaluate(qt)
+    t1 = plan.evaluate_transposed(qt)
+    # one plan's passes share its workspace: the pass on another stream
+    # starts once the passes above have finished
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        u3, f3 = plan.evaluate(qt, stream=side)
+    side.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    plan.set_tiles()
+    assert torch.equal(u1, u2) and torch.equal(f1, f2)
+    assert torch.equal(t1[0], t2[0]) and torch.equal(t1[1], t2[1])
+    assert torch.equal(u3, u2) and torch.equal(f3, f2)
+    assert torch.equal(g.pot[0], u2) and torch.equal(g.field[0], f2)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tiles(near_stream=3)
+
+
 def test_m2l_one_lane_form_where_no_shared_form_is_built(fmm):
     pos, _ = workloads.uniform_cube(5000, 3)
     pt = torch.from_numpy(pos).cuda()

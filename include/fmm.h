@@ -322,7 +322,9 @@ fmm_status fmm_plan_get_lists(const fmm_plan* plan, int64_t* m2l_src,
  *   pos      device, double[n][3], all sources
  *   q        device, [n] double (FMM_FP64) or float (FMM_FP32)
  *   targets  device, int64[ntargets] indices into pos, or NULL for all n
- *            points (then ntargets must equal n)
+ *            points (then ntargets must equal n); an index outside [0, n)
+ *            reads no memory and gives NaN outputs (the indices live on the
+ *            device, so they are checked there)
  *   pot      device, [ntargets] of the charge type
  *   field    device, [ntargets][3] (-grad u) or NULL
  * Pairs at distance 0 are skipped.  O(n * ntargets) work, enqueued on

@@ -27,7 +27,9 @@ __global__ __launch_bounds__(kTile) void k_direct(
   __shared__ T sq[kTile];
   const int64_t it = (int64_t)blockIdx.x * kTile + threadIdx.x;
   const bool live = it < nt;
-  const int64_t ti = live ? (targets ? targets[it] : it) : 0;
+  const int64_t t0 = live ? (targets ? targets[it] : it) : 0;
+  const bool inside = t0 >= 0 && t0 < n;  // an index outside [0, n) reads nothing
+  const int64_t ti = inside ? t0 : 0;
   const double xi = pos[3 * ti], yi = pos[3 * ti + 1], zi = pos[3 * ti + 2];
   T u = T(0), gx = T(0), gy = T(0), gz = T(0);
   for (int64_t base = 0; base < n; base += kTile) {
@@ -61,12 +63,13 @@ __global__ __launch_bounds__(kTile) void k_direct(
     }
   }
   if (live) {
-    pot[it] = -T(kInv4Pi) * u;
+    const T bad = __builtin_nan("");
+    pot[it] = inside ? -T(kInv4Pi) * u : bad;
     if (FIELD) {
       // field = -grad u = -(1/4pi) sum q (x_i - x_j)/r^3
-      field[3 * it] = -T(kInv4Pi) * gx;
-      field[3 * it + 1] = -T(kInv4Pi) * gy;
-      field[3 * it + 2] = -T(kInv4Pi) * gz;
+      field[3 * it] = inside ? -T(kInv4Pi) * gx : bad;
+      field[3 * it + 1] = inside ? -T(kInv4Pi) * gy : bad;
+      field[3 * it + 2] = inside ? -T(kInv4Pi) * gz : bad;
     }
   }
 }

@@ -191,6 +191,30 @@ def test_direct_kernel_matches_oracle_direct(fmm, prec):
     assert _rel(ua.double().cpu().numpy(), ud) <= tol
 
 
+def test_direct_rejects_out_of_range_targets_without_reading(fmm):
+    """Through the C ABI (the Python wrapper refuses such indices first):
+    target indices outside [0, n) read no memory and give NaN outputs; the
+    valid ones are unaffected."""
+    import ctypes
+    from paper_2511_15269_amd import _lib
+    pos, q = workloads.uniform_cube(500, 8)
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda()
+    tg = torch.tensor([-1, 7, 500, 1 << 40, 499], dtype=torch.int64, device="cuda")
+    pot = torch.empty(5, dtype=torch.float64, device="cuda")
+    fld = torch.empty((5, 3), dtype=torch.float64, device="cuda")
+    _lib.check(_lib.lib().fmm_direct(ctypes.c_void_p(pt.data_ptr()), 500,
+                                     ctypes.c_void_p(qt.data_ptr()), _lib.FMM_FP64,
+                                     ctypes.c_void_p(tg.data_ptr()), 5,
+                                     ctypes.c_void_p(pot.data_ptr()),
+                                     ctypes.c_void_p(fld.data_ptr()), None))
+    torch.cuda.synchronize()
+    bad = torch.tensor([True, False, True, True, False], device="cuda")
+    assert torch.isnan(pot[bad]).all() and torch.isnan(fld[bad]).all()
+    u, f = fmm.direct(pt, qt, torch.tensor([7, 499], device="cuda"))
+    assert torch.equal(pot[~bad], u) and torch.equal(fld[~bad], f)
+
+
 def test_stage_profile_counts_passes(fmm):
     pos, q = workloads.uniform_cube(20000, 7)
     plan = fmm.Plan(torch.from_numpy(pos).cuda(), p=6, leaf_max=64, splits=2, theta=0.6)

@@ -23,7 +23,8 @@ from ._lib import (ALLOC_FN, FMM_FP32, FMM_FP64, FMM_NSTAGES, FMM_PLAN_NO_WORKSP
                    check, lib)
 
 __all__ = ["Plan", "Graph", "FMMError", "params", "direct", "STAGES", "FMMPotential",
-           "fmm_energy", "workspace_bytes", "torch_allocator"]
+           "fmm_energy", "workspace_bytes", "torch_allocator", "tile_cache_key",
+           "read_tile_cache", "write_tile_cache"]
 
 
 @contextlib.contextmanager
@@ -75,6 +76,54 @@ def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = No
                                ctypes.c_void_p(fld.data_ptr()) if fld is not None else None,
                                _stream_ptr(None)))
     return pot, fld
+
+
+TILE_FIELDS = ("p2p_groups", "leaves_per_wave", "m2l_waves", "chain_waves", "near_stream")
+
+
+def tile_cache_key(arch: str, prm: FmmParams, n: int, kind: str = "single") -> str:
+    """Key of a tile choice in an autotune cache file: the GPU architecture
+    (its name up to the first ':'), the order, precision, vectors per pass,
+    splits, leaf size, theta, list kind and plan kind, and N rounded to a
+    power of two."""
+    size = int(round(np.log2(max(int(n), 1))))
+    prec = "fp32" if prm.precision == FMM_FP32 else "fp64"
+    lists = "same" if prm.lists == 1 else "cross"
+    return (f"{arch.split(':')[0]}|p{prm.p}|{prec}|R{prm.max_rhs}|s{prm.splits}|"
+            f"leaf{prm.leaf_max}|theta{prm.theta:.6g}|{lists}|{kind}|n2^{size}")
+
+
+def read_tile_cache(path: str) -> dict:
+    """The choices stored in an autotune cache file ({} when the file is
+    missing or not a JSON object)."""
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    return data if isinstance(data, dict) else {}
+
+
+def write_tile_cache(path: str, key: str, tiles: dict) -> None:
+    """Add (or replace) one choice in an autotune cache file; the file is
+    rewritten whole through a temporary file and a rename, so readers see
+    either the old or the new contents."""
+    import json
+    import os
+    import tempfile
+    data = read_tile_cache(path)
+    data[key] = {k: int(tiles[k]) for k in TILE_FIELDS if k in tiles}
+    d = os.path.dirname(os.path.abspath(path))
+    fd, tmp = tempfile.mkstemp(prefix=".tiles", dir=d)
+    try:
+        with os.fdopen(fd, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except BaseException:
+        if os.path.exists(tmp):
+            os.unlink(tmp)
+        raise
 
 
 def params(p=8, leaf_max=128, splits=2, theta=0.7, max_depth=16,
@@ -311,17 +360,43 @@ class Plan:
                                              ctypes.c_void_p(fld.data_ptr()) if fld is not None
                                              else None, _stream_ptr(stream)))
 
-    def autotune(self, q: torch.Tensor, stream=None) -> dict:
-        """Time the near-field source groups and the P2M/L2P leaves per wave
-        on charges ``q`` ([N], CUDA, plan precision) and keep the fastest
-        (fmm_plan_autotune).  Returns the chosen values."""
+    def autotune(self, q: torch.Tensor, stream=None, cache: str | None = None) -> dict:
+        """Time the launch tiles (fmm_tiles) on charges ``q`` ([N], CUDA,
+        plan precision) and keep the fastest (fmm_plan_autotune).  Returns
+        the chosen values.
+
+        ``cache``: path of a JSON file of earlier choices keyed by
+        tile_cache_key (GPU architecture, order, precision, vectors per
+        pass, splits, leaf size, theta, list kind, plan kind and the size
+        class of N).  A hit sets the stored tiles without timing (unless
+        this plan cannot use them); a miss times them and adds the choice
+        to the file."""
+        key = None
+        if cache is not None:
+            key = tile_cache_key(torch.cuda.get_device_properties(self.device).gcnArchName,
+                                 self._prm, self.n, self._kind())
+            hit = read_tile_cache(cache).get(key)
+            if hit is not None:
+                try:
+                    self.set_tiles(**{k: int(hit[k]) for k in TILE_FIELDS if k in hit})
+                    return self.tiles()
+                except (FMMError, TypeError, ValueError):
+                    pass  # stored for a plan whose leaves allowed other tiles
         g, lw = ctypes.c_int(), ctypes.c_int()
         with _on(self.device, stream):
             qq = self._vec(q, "q")
             check(lib().fmm_plan_autotune(self._h, ctypes.c_void_p(qq.data_ptr()),
                                           _stream_ptr(None), ctypes.byref(g),
                                           ctypes.byref(lw)))
-        return self.tiles()
+        chosen = self.tiles()
+        if key is not None:
+            write_tile_cache(cache, key, chosen)
+        return chosen
+
+    def _kind(self) -> str:
+        if self.separate:
+            return "st"
+        return "multi" if hasattr(self, "offsets") else "single"
 
     def tiles(self) -> dict:
         """Launch tiles the evaluations use (fmm_plan_get_tiles)."""

@@ -645,6 +645,34 @@ def test_m2l_one_lane_form_where_no_shared_form_is_built(fmm):
         assert plan.tiles()["m2l_waves"] == 1
 
 
+def test_autotune_cache_file_is_written_and_reused(fmm, tmp_path):
+    """A cache miss times the tiles and stores them; a second plan of the
+    same kind takes them from the file without timing."""
+    from paper_2511_15269_amd import _lib
+    path = str(tmp_path / "tiles.json")
+    pos, q = workloads.uniform_cube(30000, 81)
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda()
+    a = fmm.Plan(pt, p=6, leaf_max=32, splits=3, theta=0.7)
+    chosen = a.autotune(qt, cache=path)
+    stored = fmm.read_tile_cache(path)
+    assert len(stored) == 1 and list(stored.values())[0] == chosen
+    b = fmm.Plan(pt, p=6, leaf_max=32, splits=3, theta=0.7)
+    lib = _lib.lib()
+    real = lib.fmm_plan_autotune
+
+    def refuse(*args):
+        raise AssertionError("the cache hit must not time the tiles")
+    lib.fmm_plan_autotune = refuse
+    try:
+        assert b.autotune(qt, cache=path) == chosen
+    finally:
+        lib.fmm_plan_autotune = real
+    ua, fa = a.evaluate(qt)
+    ub, fb = b.evaluate(qt)
+    assert torch.equal(ua, ub) and torch.equal(fa, fb)
+
+
 @pytest.mark.parametrize("prec,n,p,leaf,s,theta", [("fp64", 30000, 5, 64, 2, 0.6),
                                                    ("fp32", 25000, 6, 32, 2, 0.7)])
 def test_split_near_field_lists_match_oracle(fmm, prec, n, p, leaf, s, theta):

@@ -418,6 +418,8 @@ void alloc_workspace(fmm_plan* pl, hipStream_t st) {
     const size_t ni =
         (size_t)std::max<int64_t>(std::max(pl->lists[0].n_items, pl->lists[1].n_items), 1);
     pl->bpart = plan_alloc(pl, (size_t)batch_width() * sizeof(float) * K * ni);
+    pl->iperm = (int32_t*)plan_alloc(pl, sizeof(int32_t) * (size_t)pl->n);
+    make_iperm(pl, st);
   }
   pl->tables = get_tables(prm->p, prm->precision, pl->device);
   FMM_HIP(hipStreamSynchronize(st));

@@ -64,6 +64,30 @@ __device__ __forceinline__ void neumaier16(floatx16& s, floatx16& c, floatx16 x)
 }
 
 // charges to leaf order, vectors innermost (zero past the last vector)
+// The sort stage: the caller's charges (vector-major [R][n], input order)
+// to leaf order with the 32 vectors innermost ([n][32], zero beyond R), for
+// P2M and P2P.  Block = 64 consecutive input indices: their R rows are read
+// as 256-byte runs into an LDS tile, then each point's 32 charges go out as
+// one 128-byte row at its leaf position (iperm).
+__global__ __launch_bounds__(256) void k_bgather(int64_t n, int R,
+                                                 const int32_t* __restrict__ iperm,
+                                                 const float* __restrict__ q,
+                                                 float* __restrict__ qL) {
+  __shared__ float T[kRB][64 + 1];
+  const int64_t o0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < kRB * 64; e += blockDim.x) {
+    const int r = e / 64, c = e % 64;
+    const int64_t o = o0 + c;
+    T[r][c] = (r < R && o < n) ? q[(int64_t)r * n + o] : 0.f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * kRB; e += blockDim.x) {
+    const int c = e / kRB, r = e % kRB;
+    const int64_t o = o0 + c;
+    if (o < n) qL[(int64_t)iperm[o] * kRB + r] = T[r][c];
+  }
+}
+
 // P2M as a contraction on the matrix cores: C[k][r] = normc_k sum_p
 // R_k(y_p) q[p][r] for the 32 vectors r.  The basis values of up to 64
 // points are formed in LDS (one lane per point); then v_mfma_f32_32x32x2f32
@@ -71,15 +95,12 @@ __device__ __forceinline__ void neumaier16(floatx16& s, floatx16& c, floatx16 x)
 // of three) x 2 points, B = charges of the 2 points x 32 vectors.
 // Accumulator register v of lane l holds coefficient row
 // 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, vector l % 32.
-// The kernel also does the sort stage: it gathers the charges of the leaf's
-// points from the caller's layout (vector-major, input order) and writes
-// them leaf-ordered, 32 vectors innermost and zero beyond R, for P2P.
+// The charges come leaf-ordered from k_bgather.
 template <int P>
 __global__ __launch_bounds__(64) void k_bp2m(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
-    const double* __restrict__ zs, int64_t n, int R, const int32_t* __restrict__ perm,
-    const float* __restrict__ q, float* __restrict__ qL,
+    const double* __restrict__ zs, const float* __restrict__ qL,
     const double* __restrict__ cx, const double* __restrict__ cy,
     const double* __restrict__ cz, const double* __restrict__ scale,
     const float* __restrict__ tab, float* __restrict__ C) {
@@ -109,12 +130,7 @@ __global__ __launch_bounds__(64) void k_bp2m(
       regular_basis<P, float>(float((xs[jj] - ox) * ir), float((ys[jj] - oy) * ir),
                               float((zs[jj] - oz) * ir),
                               [&](int k, float v) { B[lane][k] = pt ? v : 0.f; });
-      for (int e = lane; e < cnt * kRB; e += 64) {
-        const int pj = e / kRB, r = e % kRB;
-        const float v = r < R ? q[(int64_t)r * n + perm[c0 + pj]] : 0.f;
-        Q[pj][r] = v;
-        qL[(int64_t)c0 * kRB + e] = v;
-      }
+      for (int e = lane; e < cnt * kRB; e += 64) Q[e / kRB][e % kRB] = qL[(int64_t)c0 * kRB + e];
     }
     __syncthreads();
     for (int p0 = 0; p0 < cnt; p0 += 2) {
@@ -411,20 +427,47 @@ __global__ __launch_bounds__(64 * TW) void k_bp2p(
   }
 }
 
-// leaf-ordered [n][kRB] results to the caller's [R][n] and [R][n][3]
-__global__ void k_bscatter(int64_t n, int R, const int32_t* __restrict__ perm,
-                           const float* __restrict__ potL, const float* __restrict__ fldL,
-                           float* __restrict__ pot, float* __restrict__ field) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * kRB) return;
-  const int64_t j = e / kRB;
-  const int r = (int)(e - j * kRB);
-  if (r >= R) return;
-  const int64_t o = perm[j];
-  pot[(int64_t)r * n + o] = potL[e];
+// Leaf-ordered [n][32] results to the caller's [R][n] and [R][n][3].
+// Block = 64 consecutive output (input-order) indices: each point's
+// 32-vector rows are read as 128-byte runs from its leaf position (iperm)
+// into LDS tiles, then every vector's outputs for the 64 points go out as
+// contiguous runs (256 bytes of potential, 768 bytes of field).
+__global__ __launch_bounds__(256) void k_bscatter(int64_t n, int R,
+                                                  const int32_t* __restrict__ iperm,
+                                                  const float* __restrict__ potL,
+                                                  const float* __restrict__ fldL,
+                                                  float* __restrict__ pot,
+                                                  float* __restrict__ field) {
+  __shared__ float U[64][kRB + 1];
+  __shared__ float F[3 * 64][kRB + 1];
+  const int64_t o0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * kRB; e += blockDim.x) {
+    const int c = e / kRB, r = e % kRB;
+    const int64_t o = o0 + c;
+    U[c][r] = o < n ? potL[(int64_t)iperm[o] * kRB + r] : 0.f;
+  }
   if (field)
-    for (int a = 0; a < 3; ++a)
-      field[((int64_t)r * n + o) * 3 + a] = fldL[(j * 3 + a) * kRB + r];
+    for (int e = threadIdx.x; e < 3 * 64 * kRB; e += blockDim.x) {
+      const int ca = e / kRB, r = e % kRB;
+      const int64_t o = o0 + ca / 3;
+      F[ca][r] = o < n ? fldL[((int64_t)iperm[o] * 3 + ca % 3) * kRB + r] : 0.f;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kRB * 64; e += blockDim.x) {
+    const int r = e / 64, c = e % 64;
+    if (r < R && o0 + c < n) pot[(int64_t)r * n + o0 + c] = U[c][r];
+  }
+  if (field)
+    for (int e = threadIdx.x; e < kRB * 3 * 64; e += blockDim.x) {
+      const int r = e / (3 * 64), ca = e % (3 * 64);
+      if (r < R && o0 + ca / 3 < n) field[((int64_t)r * n + o0) * 3 + ca] = F[ca][r];
+    }
+}
+
+// iperm[perm[j]] = j: leaf position of every input index
+__global__ void k_invert(int64_t n, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) iperm[perm[j]] = (int32_t)j;
 }
 
 template <int P>
@@ -444,8 +487,9 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   mk.begin(kStSort, st);
   mk.end(kStSort, st);
   mk.begin(kStP2M, st);
+  k_bgather<<<blocks(n, 64), 256, 0, st>>>(n, R, pl->iperm, q, qL);
   k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
-                                                pl->zs, n, R, pl->perm, q, qL, pl->cx, pl->cy, pl->cz, pl->scale,
+                                                pl->zs, qL, pl->cx, pl->cy, pl->cz, pl->scale,
                                                 tab, C);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
@@ -486,7 +530,7 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
     else if (TW == 4) p2p(k_bp2p<4>, 4);
     else p2p(k_bp2p<8>, 8);
   }
-  k_bscatter<<<blocks(n * kRB, 256), 256, 0, st>>>(n, R, pl->perm, potL, fldL, pot, field);
+  k_bscatter<<<blocks(n, 64), 256, 0, st>>>(n, R, pl->iperm, potL, fldL, pot, field);
   mk.end(kStP2P, st);
   FMM_HIP(hipGetLastError());
 }
@@ -494,6 +538,11 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
 }  // namespace
 
 int batch_width() { return kRB; }
+
+void make_iperm(fmm_plan* pl, hipStream_t st) {
+  k_invert<<<blocks(pl->n, 256), 256, 0, st>>>(pl->n, pl->perm, pl->iperm);
+  FMM_HIP(hipGetLastError());
+}
 
 void evaluate_batch(fmm_plan* pl, int dir, const float* q, int R, float* pot, float* field,
                     hipStream_t st) {

@@ -220,6 +220,8 @@ struct fmm_plan {
   // batched M2L partial rows [n_items][K][32] (FP32 plans with max_rhs > 1);
   // sized by the lists, so held with them
   void* bpart = nullptr;
+  // batched plans: leaf position of every input index (inverse of perm)
+  int32_t* iperm = nullptr;
   const void* tables = nullptr;  // device operator tables for (p, precision)
 
   std::vector<fmm::DevBuf> bufs;
@@ -322,6 +324,8 @@ void evaluate(fmm_plan* pl, const Workspace& ws, int dir, const void* q, int nrh
               void* field, hipStream_t st);
 // Up to batch_width() FP32 charge vectors in one pass (batch.hip).
 int batch_width();
+// iperm of a batched plan from its perm (on st)
+void make_iperm(fmm_plan* pl, hipStream_t st);
 void evaluate_batch(fmm_plan* pl, int dir, const float* q, int R, float* pot, float* field,
                     hipStream_t st);
 // Adjoint combine: grad_x = -(g * field_fwd + q * field_t) (eval.hip).

@@ -13,7 +13,8 @@
 //         forms C[k][r] = sum_i B_k(y_i) q_i[r].
 //   M2M, M2L, L2L: the single-vector rotate / z-shift / rotate-back code,
 //         one (box or work item, vector) per lane, two boxes or items per
-//         wave (one per half-wave).
+//         wave (one per half-wave); M2M translates the children of a parent
+//         in parallel waves and adds them in child order.
 //   L2P:  block = leaf; basis and gradient of 32 points in LDS, lane r
 //         forms the potential and gradient sums.
 //   P2P:  a dense contraction: for a tile of 32 targets and pairs of source
@@ -151,34 +152,44 @@ __global__ __launch_bounds__(64) void k_bp2m(
     }
 }
 
-// parent += M2M(child) over the 2^s children; one (parent, vector) per lane
+// parent = sum over its 2^s children of M2M(child), 32 vectors per parent:
+// wave c of a block of 2^s waves translates child c of two parents (one
+// per half-wave, lane = vector), and the translated children are added in
+// child order through an LDS tile (one barrier per child).
 template <int P>
-__global__ __launch_bounds__(64) void k_bm2m(
+__global__ __launch_bounds__(512) void k_bm2m_par(
     int64_t npar, const int32_t* __restrict__ par, const int32_t* __restrict__ child0, int s,
-    const double* __restrict__ cx,
-    const double* __restrict__ cy, const double* __restrict__ cz,
-    const double* __restrict__ scale, const float* __restrict__ tab, float* C) {
+    const double* __restrict__ cx, const double* __restrict__ cy,
+    const double* __restrict__ cz, const double* __restrict__ scale,
+    const float* __restrict__ tab, float* C) {
   constexpr int K = K_<P>::value;
-  const int64_t b = (int64_t)blockIdx.x * 2 + threadIdx.x / kRB;
-  const int r = threadIdx.x % kRB;
-  if (b >= npar) return;
-  const int64_t pa = par[b];
-  float acc[K];
+  __shared__ float A[2][K][kRB];
+  const int c = threadIdx.x / 64;  // child (wave-uniform)
+  const int lane = threadIdx.x % 64;
+  const int h = lane / kRB, r = lane % kRB;
+  const int64_t b = (int64_t)blockIdx.x * 2 + h;
+  const bool live = b < npar;
+  const int64_t pa = live ? par[b] : 0;
+  const int64_t ch = live ? child0[b] + c : 0;
+  float v[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.f;
-  const int nch = 1 << s;
-  for (int c = 0; c < nch; ++c) {
-    const int64_t ch = child0[b] + c;
-    float v[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = C[(ch * K + k) * kRB + r];
+  for (int k = 0; k < K; ++k) v[k] = live ? C[(ch * K + k) * kRB + r] : 0.f;
+  if (live)
     rotate_shift<P, kM2M, float>(v, cx[ch] - cx[pa], cy[ch] - cy[pa], cz[ch] - cz[pa],
                                  scale[ch], scale[pa], tab);
+  const int nch = 1 << s;
+  for (int step = 0; step < nch; ++step) {
+    if (c == step) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v[k];
+      for (int k = 0; k < K; ++k) A[h][k][r] = (step == 0 ? 0.f : A[h][k][r]) + v[k];
+    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int k = 0; k < K; ++k) C[(pa * K + k) * kRB + r] = acc[k];
+  for (int e = threadIdx.x; e < 2 * K * kRB; e += blockDim.x) {
+    const int hh = e / (K * kRB), kr = e % (K * kRB);
+    const int64_t bb = (int64_t)blockIdx.x * 2 + hh;
+    if (bb < npar) C[(int64_t)par[bb] * K * kRB + kr] = A[hh][kr / kRB][kr % kRB];
+  }
 }
 
 template <int P>
@@ -494,8 +505,8 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
   for (const Step& S : pl->side[0].m2m_steps)
-    k_bm2m<P><<<blocks(S.n, 2), 64, 0, st>>>(S.n, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
-                                             pl->scale, tab, C);
+    k_bm2m_par<P><<<blocks(S.n, 2), 64 << s, 0, st>>>(S.n, S.a, S.b, s, pl->cx, pl->cy, pl->cz,
+                                                      pl->scale, tab, C);
   mk.end(kStM2M, st);
   mk.begin(kStM2L, st);
   if (Ls.n_items > 0)

@@ -354,9 +354,11 @@ fmm_status fmm_plan_read_profile(fmm_plan* plan, double* stage_ms,
  * lane or several waves per translation) and the near field's stream, then
  * the number of source groups of the near-field kernel (1, 2 or 4) together
  * with the number of leaves per wave of P2M and L2P (1, 2, 4 or 8), among
- * the values the plan's largest leaf allows.  Every candidate runs one
- * untimed and three timed evaluations of the charges q (device, [n], the
- * plan's precision) on `stream`; the fastest values are stored in the plan
+ * the values the plan's largest leaf allows; on plans of the 32-vector form
+ * (FP32, max_rhs > 1) also the batched near field's waves per block, timed
+ * on passes of max_rhs copies of q.  Every candidate runs one untimed and
+ * three timed evaluations of the charges q (device, [n], the plan's
+ * precision) on `stream`; the fastest values are stored in the plan
  * and used by every later evaluation (results change only by the summation
  * order inside the near field and the multipole sums).  The chosen groups
  * and leaves per wave are written to *p2p_groups and *leaves_per_wave
@@ -380,6 +382,12 @@ fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p
  *   chain_waves      waves sharing each M2M and L2L translation: 1 (one
  *                    lane per translation) or 4 (the shared form, built and
  *                    the default for p >= 5).  Identical results.
+ *   batch_p2p_waves  waves per block of the 32-vector near field (each
+ *                    takes 16 targets of the leaf at a time, the block's
+ *                    waves share every staged source chunk): 1, 2, 4 or 8;
+ *                    by default set from the plan's largest leaf.  Identical
+ *                    results.  Read and set on every plan; used by plans
+ *                    with max_rhs > 1 in FP32.
  *   near_stream      2 (default): the near field runs on a second stream
  *                    of the plan beside the far-field chain (M2M, M2L,
  *                    L2L), forked after P2M and joined before L2P; 1: every
@@ -397,6 +405,7 @@ typedef struct fmm_tiles {
   int m2l_waves;
   int chain_waves;
   int near_stream;
+  int batch_p2p_waves;
 } fmm_tiles;
 fmm_status fmm_plan_set_tiles(fmm_plan* plan, const fmm_tiles* tiles);
 fmm_status fmm_plan_get_tiles(const fmm_plan* plan, fmm_tiles* tiles);

@@ -78,7 +78,8 @@ def direct(pos: torch.Tensor, q: torch.Tensor, targets: torch.Tensor | None = No
     return pot, fld
 
 
-TILE_FIELDS = ("p2p_groups", "leaves_per_wave", "m2l_waves", "chain_waves", "near_stream")
+TILE_FIELDS = ("p2p_groups", "leaves_per_wave", "m2l_waves", "chain_waves", "near_stream",
+               "batch_p2p_waves")
 
 
 def tile_cache_key(arch: str, prm: FmmParams, n: int, kind: str = "single") -> str:
@@ -404,12 +405,14 @@ class Plan:
         check(lib().fmm_plan_get_tiles(self._h, ctypes.byref(t)))
         return {"p2p_groups": t.p2p_groups, "leaves_per_wave": t.leaves_per_wave,
                 "m2l_waves": t.m2l_waves, "chain_waves": t.chain_waves,
-                "near_stream": t.near_stream}
+                "near_stream": t.near_stream, "batch_p2p_waves": t.batch_p2p_waves}
 
     def set_tiles(self, p2p_groups: int = 0, leaves_per_wave: int = 0,
-                  m2l_waves: int = 0, chain_waves: int = 0, near_stream: int = 0) -> None:
+                  m2l_waves: int = 0, chain_waves: int = 0, near_stream: int = 0,
+                  batch_p2p_waves: int = 0) -> None:
         """Set the launch tiles (0: the plan's default; fmm_plan_set_tiles)."""
-        t = FmmTiles(p2p_groups, leaves_per_wave, m2l_waves, chain_waves, near_stream)
+        t = FmmTiles(p2p_groups, leaves_per_wave, m2l_waves, chain_waves, near_stream,
+                     batch_p2p_waves)
         check(lib().fmm_plan_set_tiles(self._h, ctypes.byref(t)))
 
     def set_profiling(self, on: bool = True) -> None:

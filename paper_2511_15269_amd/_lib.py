@@ -40,7 +40,7 @@ class FmmPlanInfo(ctypes.Structure):
 class FmmTiles(ctypes.Structure):
     _fields_ = [("p2p_groups", ctypes.c_int), ("leaves_per_wave", ctypes.c_int),
                 ("m2l_waves", ctypes.c_int), ("chain_waves", ctypes.c_int),
-                ("near_stream", ctypes.c_int)]
+                ("near_stream", ctypes.c_int), ("batch_p2p_waves", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -848,14 +848,18 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
     const size_t es = pl->prm.precision == FMM_FP32 ? sizeof(float) : sizeof(double);
     void* pot = nullptr;
     void* fld = nullptr;
+    void *qb = nullptr, *pb = nullptr, *fb = nullptr;  // 32-vector timing buffers
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool prof = pl->profiling;
     const int g0 = pl->p2p_groups, l0 = pl->leaves_per_wave, w0 = pl->m2l_waves,
-              c0 = pl->chain_waves, s0 = pl->near_stream;
+              c0 = pl->chain_waves, s0 = pl->near_stream, b0 = pl->batch_p2p_waves;
     auto cleanup = [&] {
-      if (pot || fld) (void)hipStreamSynchronize(st);
+      if (pot || fld || qb || pb || fb) (void)hipStreamSynchronize(st);
       dev_free(pl, pot);
       dev_free(pl, fld);
+      dev_free(pl, qb);
+      dev_free(pl, pb);
+      dev_free(pl, fb);
       if (e0) (void)hipEventDestroy(e0);
       if (e1) (void)hipEventDestroy(e1);
       pl->profiling = prof;
@@ -915,12 +919,45 @@ fmm_status fmm_plan_autotune(fmm_plan* pl, const void* q, void* stream, int* gro
       }
       pl->p2p_groups = bg;
       pl->leaves_per_wave = bl;
+      if (batched_plan(pl) && pl->ws.bq) {
+        // the 32-vector pass on max_rhs copies of q
+        const int R = std::min(pl->prm.max_rhs, batch_width());
+        const size_t row = sizeof(float) * (size_t)pl->n;
+        qb = dev_alloc(pl, row * R);
+        pb = dev_alloc(pl, row * R);
+        fb = dev_alloc(pl, 3 * row * R);
+        for (int r = 0; r < R; ++r)
+          FMM_HIP(hipMemcpyAsync((char*)qb + r * row, q, row, hipMemcpyDeviceToDevice, st));
+        auto timeb = [&] {
+          evaluate_batch(pl, 0, (const float*)qb, R, (float*)pb, (float*)fb, st);
+          FMM_HIP(hipEventRecord(e0, st));
+          for (int r = 0; r < 3; ++r)
+            evaluate_batch(pl, 0, (const float*)qb, R, (float*)pb, (float*)fb, st);
+          FMM_HIP(hipEventRecord(e1, st));
+          FMM_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          FMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          return ms;
+        };
+        float bbest = -1.f;
+        int bw = 0;
+        for (int w : {1, 2, 4, 8}) {
+          pl->batch_p2p_waves = w;
+          const float ms = timeb();
+          if (bbest < 0.f || ms < bbest) {
+            bbest = ms;
+            bw = w;
+          }
+        }
+        pl->batch_p2p_waves = bw;
+      }
     } catch (...) {
       pl->p2p_groups = g0;
       pl->leaves_per_wave = l0;
       pl->m2l_waves = w0;
       pl->chain_waves = c0;
       pl->near_stream = s0;
+      pl->batch_p2p_waves = b0;
       cleanup();
       throw;
     }
@@ -951,9 +988,13 @@ fmm_status fmm_plan_set_tiles(fmm_plan* pl, const fmm_tiles* t) {
     pl->leaves_per_wave = t->leaves_per_wave;
     if (t->near_stream != 0 && t->near_stream != 1 && t->near_stream != 2)
       throw Error{FMM_EINVAL, "near_stream must be 0, 1 or 2"};
+    if (t->batch_p2p_waves != 0 && t->batch_p2p_waves != 1 && t->batch_p2p_waves != 2 &&
+        t->batch_p2p_waves != 4 && t->batch_p2p_waves != 8)
+      throw Error{FMM_EINVAL, "batch_p2p_waves must be 0, 1, 2, 4 or 8"};
     pl->m2l_waves = t->m2l_waves == 1 ? 1 : 0;
     pl->chain_waves = t->chain_waves == 1 ? 1 : 0;
     pl->near_stream = t->near_stream == 1 ? 1 : 0;
+    pl->batch_p2p_waves = t->batch_p2p_waves;
   });
 }
 
@@ -965,6 +1006,7 @@ fmm_status fmm_plan_get_tiles(const fmm_plan* pl, fmm_tiles* t) {
     t->m2l_waves = m2l_waves(pl);
     t->chain_waves = chain_waves(pl);
     t->near_stream = pl->near_stream == 1 ? 1 : 2;
+    t->batch_p2p_waves = batch_p2p_waves(pl);
   });
 }
 

@@ -530,8 +530,7 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   mk.end(kStL2P, st);
   mk.begin(kStP2P, st);
   {
-    const int mlc = pl->max_leaf_count;
-    const int TW = mlc > 64 ? 8 : (mlc > 32 ? 4 : (mlc > 16 ? 2 : 1));
+    const int TW = batch_p2p_waves(pl);
     auto p2p = [&](auto kern, int tw) {
       kern<<<(unsigned)pl->nleaf, 64 * tw, 0, st>>>(pl->leaf_start, pl->xs, pl->ys, pl->zs, qL,
                                                      Ls.p2p_ptr, Ls.p2p_src, potL, fldL);
@@ -549,6 +548,13 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
 }  // namespace
 
 int batch_width() { return kRB; }
+
+int batch_p2p_waves(const fmm_plan* pl) {
+  const int w = pl->batch_p2p_waves;
+  if (w == 1 || w == 2 || w == 4 || w == 8) return w;
+  const int mlc = pl->max_leaf_count;
+  return mlc > 64 ? 8 : (mlc > 32 ? 4 : (mlc > 16 ? 2 : 1));
+}
 
 void make_iperm(fmm_plan* pl, hipStream_t st) {
   k_invert<<<blocks(pl->n, 256), 256, 0, st>>>(pl->n, pl->perm, pl->iperm);

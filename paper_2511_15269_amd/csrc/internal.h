@@ -198,6 +198,9 @@ struct fmm_plan {
   // 1: one lane per M2M / L2L translation; 0: shared by four waves from
   // order kChainShareMinOrder on
   int chain_waves = 0;
+  // waves per block of the batched near field (1, 2, 4, 8; 0: by the
+  // plan's largest leaf)
+  int batch_p2p_waves = 0;
   // 1: the near field on the caller's stream after the far-field chain; 0:
   // on the plan's second stream beside it
   int near_stream = 0;
@@ -324,6 +327,8 @@ void evaluate(fmm_plan* pl, const Workspace& ws, int dir, const void* q, int nrh
               void* field, hipStream_t st);
 // Up to batch_width() FP32 charge vectors in one pass (batch.hip).
 int batch_width();
+// waves per block of the batched near field for this plan
+int batch_p2p_waves(const fmm_plan* pl);
 // iperm of a batched plan from its perm (on st)
 void make_iperm(fmm_plan* pl, hipStream_t st);
 void evaluate_batch(fmm_plan* pl, int dir, const float* q, int R, float* pot, float* field,

@@ -200,8 +200,8 @@ def test_create_st_checks_arguments_first():
 
 def test_tiles_null_arguments():
     lib = L.lib()
-    t = L.FmmTiles(1, 1, 1, 1, 1)
+    t = L.FmmTiles(1, 1, 1, 1, 1, 1)
     assert lib.fmm_plan_set_tiles(None, ctypes.byref(t)) == L.FMM_EINVAL
     assert lib.fmm_plan_get_tiles(None, ctypes.byref(t)) == L.FMM_EINVAL
     assert (t.p2p_groups, t.leaves_per_wave, t.m2l_waves, t.chain_waves,
-            t.near_stream) == (1, 1, 1, 1, 1)
+            t.near_stream, t.batch_p2p_waves) == (1, 1, 1, 1, 1, 1)

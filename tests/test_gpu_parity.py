@@ -455,6 +455,34 @@ def test_multi_plan_matches_separate_plans_and_oracle(fmm, prec, sizes, kinds, p
     assert np.array_equal(pps, p_all[0][o]) and np.array_equal(ppt, p_all[1][o])
 
 
+def test_batched_near_field_waves_give_identical_results_and_are_tuned(fmm):
+    """The batched near field's waves per block only change how the 16-target
+    tiles of a leaf are shared out: every choice gives the same bits, and
+    autotune picks one of them."""
+    _say("[batched waves]")
+    pos, Q = workloads.uniform_cube(40000, 17, nrhs=8)
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(Q).cuda().float()
+    plan = fmm.Plan(pt, p=6, leaf_max=96, splits=2, theta=0.7, precision="fp32", max_rhs=8)
+    assert plan.tiles()["batch_p2p_waves"] in (1, 2, 4, 8)
+    ref = None
+    for w in (1, 2, 4, 8):
+        plan.set_tiles(batch_p2p_waves=w)
+        assert plan.tiles()["batch_p2p_waves"] == w
+        u, f = plan.evaluate(qt)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (u, f)
+        else:
+            assert torch.equal(u, ref[0]) and torch.equal(f, ref[1])
+    with pytest.raises(fmm.FMMError):
+        plan.set_tiles(batch_p2p_waves=3)
+    choice = plan.autotune(qt[0])
+    assert choice["batch_p2p_waves"] in (1, 2, 4, 8)
+    u, f = plan.evaluate(qt)
+    assert torch.equal(u, ref[0]) and torch.equal(f, ref[1])
+
+
 def test_multi_plan_batched_vectors(fmm):
     """Uneven problems and several charge vectors at once (FP32)."""
     sizes = [6000, 500, 13000]

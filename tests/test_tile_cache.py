@@ -25,7 +25,7 @@ def test_write_then_read_round_trip(tmp_path):
     path = str(tmp_path / "tiles.json")
     assert fmm.read_tile_cache(path) == {}
     t = {"p2p_groups": 2, "leaves_per_wave": 2, "m2l_waves": 1, "chain_waves": 4,
-         "near_stream": 2, "unrelated": 9}
+         "near_stream": 2, "batch_p2p_waves": 4, "unrelated": 9}
     fmm.write_tile_cache(path, "a", t)
     fmm.write_tile_cache(path, "b", dict(t, p2p_groups=4))
     got = fmm.read_tile_cache(path)

@@ -383,6 +383,8 @@ def run_batched(F, torch, dev, args, timed, rel, n=1 << 18, R=32):
               precision="fp32")
     plan = F.Plan(pos_d, max_rhs=R, **kw)
     single = F.Plan(pos_d, **kw)
+    tiles = plan.autotune(Qd[0])
+    single.autotune(Qd[0])
     pot = torch.empty((R, n), dtype=torch.float32, device=dev)
     fld = torch.empty((R, n, 3), dtype=torch.float32, device=dev)
     ms_b = timed(lambda: plan.evaluate(Qd, out=(pot, fld)), args.steps, args.warmup)
@@ -402,7 +404,7 @@ def run_batched(F, torch, dev, args, timed, rel, n=1 << 18, R=32):
         acc[f"rel_l2_field_v{r}"] = rel(fld[r].double().cpu().numpy()[tg], fd.cpu().numpy())
     out = {
         f"fwd_fp32_batched{R}_n{n}": {"ms_per_step": ms_b, "mpoints_s": R * n / ms_b / 1e3,
-                                      "vectors": R, **acc},
+                                      "vectors": R, "tiles": tiles, **acc},
         f"fwd_fp32_{R}x_single_n{n}": {"ms_per_step": ms_s, "mpoints_s": R * n / ms_s / 1e3,
                                        "vectors": R},
     }
@@ -509,7 +511,7 @@ def counters_run(args, pos, q):
         plan = F.Plan(torch.from_numpy(pos).to(dev), p=args.p, leaf_max=args.leaf,
                       splits=args.splits, theta=args.theta, precision="fp32", max_rhs=R)
         Qd = torch.from_numpy(Q).to(dev).float()
-        tiles = None
+        tiles = plan.autotune(Qd[0])
         pot = torch.empty((R, n), dtype=torch.float32, device=dev)
         fld = torch.empty((R, n, 3), dtype=torch.float32, device=dev)
         for _ in range(args.warmup + args.steps):

@@ -325,11 +325,13 @@ __global__ __launch_bounds__(64) void k_bl2p(
 // 32 charges) are staged in LDS, up to kStage points at a time, with
 // coalesced loads.  A block holds TW waves, one 16-target tile each, that
 // share every staged chunk.  Small tiles keep the accumulators to 32
-// registers per lane, so two waves share a SIMD.
+// registers per lane; the kernel is held to three waves per SIMD (146
+// registers, no spills), so that the kernel values of one wave's next step
+// are computed while another wave's MFMAs run.
 constexpr int kStage = 64;
 
 template <int TW>
-__global__ __launch_bounds__(64 * TW) void k_bp2p(
+__global__ __launch_bounds__(64 * TW) __attribute__((amdgpu_waves_per_eu(3))) void k_bp2p(
     const int32_t* __restrict__ leaf_start, const double* __restrict__ xs,
     const double* __restrict__ ys, const double* __restrict__ zs,
     const float* __restrict__ qL, const int32_t* __restrict__ p2p_ptr,

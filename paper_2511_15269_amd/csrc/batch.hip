@@ -249,12 +249,14 @@ __global__ __launch_bounds__(64) void k_bl2l(
 // L2P as a contraction on the matrix cores: for 32 points at a time,
 // u[p][r] = sum_k R_k(y_p) w_k D[k][r] and likewise the three gradient
 // components.  The basis and its gradient are formed in LDS (one lane per
-// point); v_mfma_f32_32x32x2f32 then takes two coefficients per step:
-// A = basis values of 32 points (rows) x 2 coefficients, B = weighted local
-// coefficients (2 x 32 vectors).  Accumulator register v of lane l holds
-// point row 8 (v / 4) + 4 (l / 32) + v % 4, vector l % 32.
+// point, first wave); v_mfma_f32_32x32x2f32 then takes two coefficients per
+// step: A = basis values of 32 points (rows) x 2 coefficients, B = weighted
+// local coefficients (2 x 32 vectors).  The block's four waves share the
+// basis tile, wave c forming component c (potential, then the gradient's
+// x, y, z), so that a 43 KiB tile serves four waves.  Accumulator register
+// v of lane l holds point row 8 (v / 4) + 4 (l / 32) + v % 4, vector l % 32.
 template <int P>
-__global__ __launch_bounds__(64) void k_bl2p(
+__global__ __launch_bounds__(256) void k_bl2p(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
     const double* __restrict__ zs, const double* __restrict__ cx,
@@ -266,7 +268,8 @@ __global__ __launch_bounds__(64) void k_bl2p(
   constexpr int NP = 32;
   __shared__ float Bv[4][K2][NP + 1];
   const int leaf = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x % 64;
+  const int comp = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // component of this wave
   const int col = lane % 32, kh = lane / 32;
   const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(64) void k_bl2p(
   for (int c0 = st; c0 < en; c0 += NP) {
     const int cnt = min(NP, en - c0);
     __syncthreads();
-    if (lane < NP) {
+    if (threadIdx.x < NP) {
       const bool pt = lane < cnt;
       const int j = pt ? c0 + lane : c0;
       const float x = float((xs[j] - ox) * ir), y = float((ys[j] - oy) * ir),
@@ -292,24 +295,21 @@ __global__ __launch_bounds__(64) void k_bl2p(
       }
     }
     __syncthreads();
-    floatx16 au = {}, ax = {}, ay = {}, az = {};
+    floatx16 acc = {};
     for (int k0 = 0; k0 < K2; k0 += 2) {
       const int k = k0 + kh;
       const float b = k < K ? D[(g * K + k) * kRB + col] * tab[tab_l2p(P) + k] : 0.f;
-      au = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[0][k][col], b, au, 0, 0, 0);
-      ax = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[1][k][col], b, ax, 0, 0, 0);
-      ay = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[2][k][col], b, ay, 0, 0, 0);
-      az = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[3][k][col], b, az, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Bv[comp][k][col], b, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int pnt = 8 * (v / 4) + 4 * kh + v % 4;
       if (pnt < cnt) {
         const int64_t o = c0 + pnt;
-        potL[o * kRB + col] = fu * au[v];
-        fldL[(o * 3 + 0) * kRB + col] = ff * ax[v];
-        fldL[(o * 3 + 1) * kRB + col] = ff * ay[v];
-        fldL[(o * 3 + 2) * kRB + col] = ff * az[v];
+        if (comp == 0)
+          potL[o * kRB + col] = fu * acc[v];
+        else
+          fldL[(o * 3 + comp - 1) * kRB + col] = ff * acc[v];
       }
     }
   }
@@ -526,7 +526,7 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
                                              tab, D);
   mk.end(kStL2L, st);
   mk.begin(kStL2P, st);
-  k_bl2p<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
+  k_bl2p<P><<<(unsigned)pl->nleaf, 256, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
                                                 pl->zs, pl->cx, pl->cy, pl->cz, pl->scale, D,
                                                 tab, potL, fldL);
   mk.end(kStL2P, st);

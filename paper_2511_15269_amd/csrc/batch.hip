@@ -95,10 +95,11 @@ __global__ __launch_bounds__(256) void k_bgather(int64_t n, int R,
 // takes two points per step: A = basis of 32 coefficients (rows, one tile
 // of three) x 2 points, B = charges of the 2 points x 32 vectors.
 // Accumulator register v of lane l holds coefficient row
-// 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, vector l % 32.
-// The charges come leaf-ordered from k_bgather.
+// 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, vector l % 32.  One wave per
+// tile of 32 coefficients, the basis and charge tiles shared in LDS.  The
+// charges come leaf-ordered from k_bgather.
 template <int P>
-__global__ __launch_bounds__(64) void k_bp2m(
+__global__ __launch_bounds__(64 * ((K_<P>::value + 31) / 32)) void k_bp2m(
     const int32_t* __restrict__ leaf_box, const int32_t* __restrict__ leaf_start,
     const double* __restrict__ xs, const double* __restrict__ ys,
     const double* __restrict__ zs, const float* __restrict__ qL,
@@ -106,24 +107,24 @@ __global__ __launch_bounds__(64) void k_bp2m(
     const double* __restrict__ cz, const double* __restrict__ scale,
     const float* __restrict__ tab, float* __restrict__ C) {
   constexpr int K = K_<P>::value;
-  constexpr int NT = (K + 31) / 32;  // coefficient tiles
+  constexpr int NT = (K + 31) / 32;  // coefficient tiles, one wave each
   __shared__ float B[64][NT * 32 + 1];
   __shared__ float Q[64][kRB];  // charges of the chunk's points
   const int leaf = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x % 64;
+  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // this wave's tile
   const int col = lane % 32, kh = lane / 32;
   const int64_t g = leaf_box[leaf];
   const int st = leaf_start[leaf], en = leaf_start[leaf + 1];
   const double ox = cx[g], oy = cy[g], oz = cz[g], ir = 1.0 / scale[g];
-  floatx16 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
+  floatx16 acc = {};
   for (int c0 = st; c0 < en; c0 += 64) {
-    const int j = c0 + lane;
     const int cnt = min(64, en - c0);
     __syncthreads();
-    {
-      // padding rows and missing points read as zero
+    if (t == 0) {
+      // the first wave forms the basis (lane = point); padding rows and
+      // missing points read as zero
+      const int j = c0 + lane;
       const bool pt = j < en;
       const int jj = pt ? j : c0;
 #pragma unroll
@@ -131,25 +132,22 @@ __global__ __launch_bounds__(64) void k_bp2m(
       regular_basis<P, float>(float((xs[jj] - ox) * ir), float((ys[jj] - oy) * ir),
                               float((zs[jj] - oz) * ir),
                               [&](int k, float v) { B[lane][k] = pt ? v : 0.f; });
-      for (int e = lane; e < cnt * kRB; e += 64) Q[e / kRB][e % kRB] = qL[(int64_t)c0 * kRB + e];
     }
+    for (int e = threadIdx.x; e < cnt * kRB; e += blockDim.x)
+      Q[e / kRB][e % kRB] = qL[(int64_t)c0 * kRB + e];
     __syncthreads();
     for (int p0 = 0; p0 < cnt; p0 += 2) {
       const int pp = p0 + kh;
       const float b = pp < cnt ? Q[pp][col] : 0.f;
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(B[pp < 64 ? pp : 0][t * 32 + col], b, acc[t],
-                                                      0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(B[pp < 64 ? pp : 0][t * 32 + col], b, acc, 0, 0,
+                                                 0);
     }
   }
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int k = t * 32 + 8 * (v / 4) + 4 * kh + v % 4;
-      if (k < K) C[(g * K + k) * kRB + col] = acc[t][v] * tab[tab_normc(P) + k];
-    }
+  for (int v = 0; v < 16; ++v) {
+    const int k = t * 32 + 8 * (v / 4) + 4 * kh + v % 4;
+    if (k < K) C[(g * K + k) * kRB + col] = acc[v] * tab[tab_normc(P) + k];
+  }
 }
 
 // parent = sum over its 2^s children of M2M(child), 32 vectors per parent:
@@ -501,9 +499,9 @@ void run_batch(fmm_plan* pl, const ListSet& Ls, const float* q, int R, float* po
   mk.end(kStSort, st);
   mk.begin(kStP2M, st);
   k_bgather<<<blocks(n, 64), 256, 0, st>>>(n, R, pl->iperm, q, qL);
-  k_bp2m<P><<<(unsigned)pl->nleaf, 64, 0, st>>>(pl->leaf_box, pl->leaf_start, pl->xs, pl->ys,
-                                                pl->zs, qL, pl->cx, pl->cy, pl->cz, pl->scale,
-                                                tab, C);
+  k_bp2m<P><<<(unsigned)pl->nleaf, 64 * ((K_<P>::value + 31) / 32), 0, st>>>(
+      pl->leaf_box, pl->leaf_start, pl->xs, pl->ys, pl->zs, qL, pl->cx, pl->cy, pl->cz,
+      pl->scale, tab, C);
   mk.end(kStP2M, st);
   mk.begin(kStM2M, st);
   for (const Step& S : pl->side[0].m2m_steps)

@@ -588,7 +588,9 @@ __global__ __launch_bounds__(64 * kShareWaves) void k_l2l_fin_shared(
 // field = -grad u (an extra 1/rho from the chain rule), at every point of the
 // target leaf, added to the near field P2P left in leaf order; writes the
 // outputs in input order.  G leaves per wave, LW = 64/G lanes each, lane =
-// point.
+// point.  The gradient is evaluated from the leaf's gradient expansions
+// (grad_coeff, formed once per leaf in LDS), so every point needs only the
+// basis values.
 template <int P, typename T, bool FIELD, int G>
 __global__ __launch_bounds__(64) void k_l2p(
     int64_t nleaf, const int32_t* __restrict__ leaf_box,
@@ -599,14 +601,23 @@ __global__ __launch_bounds__(64) void k_l2p(
     const double* __restrict__ scale, const T* __restrict__ D, const T* __restrict__ tab,
     int64_t n, const T* __restrict__ near, T* __restrict__ pot, T* __restrict__ field) {
   constexpr int K = K_<P>::value;
+  constexpr int K1 = P * P;  // coefficients of the gradient expansions
   constexpr int LW = 64 / G;
   __shared__ T w[G][K];
+  __shared__ T gw[G][3][K1];
   const int lane = threadIdx.x;
   const int h = lane / LW, l = lane % LW;
   for (int idx = lane; idx < G * K; idx += 64) {
     const int hh = idx / K, k = idx - hh * K;
     const int64_t lf = (int64_t)blockIdx.x * G + hh;
     if (lf < nleaf) w[hh][k] = D[(int64_t)leaf_box[lf] * K + k] * tab[tab_l2p(P) + k];
+  }
+  if (FIELD) {
+    __syncthreads();
+    for (int idx = lane; idx < G * K1; idx += 64) {
+      const int hh = idx / K1, k = idx - hh * K1;
+      grad_coeff<P, T>(w[hh], k, gw[hh][0][k], gw[hh][1][k], gw[hh][2][k]);
+    }
   }
   __syncthreads();
   const int64_t leaf = (int64_t)blockIdx.x * G + h;
@@ -617,8 +628,8 @@ __global__ __launch_bounds__(64) void k_l2p(
   const T fu = T(-kInv4Pi * ir), ff = T(kInv4Pi * ir * ir);
   for (int i = st + l; i < en; i += LW) {
     T fp = T(0), fx = T(0), fy = T(0), fz = T(0);
-    local_eval<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir), w[h],
-                     fp, fx, fy, fz);
+    local_eval_grad<P, T>(T((xs[i] - ox) * ir), T((ys[i] - oy) * ir), T((zs[i] - oz) * ir),
+                          w[h], gw[h][0], gw[h][1], gw[h][2], fp, fx, fy, fz);
     const int o = perm[i];
     pot[o] = near[i] + fu * fp;
     if (FIELD) {

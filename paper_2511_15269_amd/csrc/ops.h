@@ -469,12 +469,103 @@ __device__ __forceinline__ void neumaier(T& s, T& c, T x) {
   s = t;
 }
 
-// pot += sum_k w[k] R-hat_k, grad += sum_k w[k] grad R-hat_k.  In FP32 the
-// terms of each order m are summed on their own and the order sums are
+// Regular basis values R-hat^m_n only, in the order-major sweeps of
+// basis_with_gradient (the same recursions, the same values); calls f(n, k,
+// value) and band_end() after the last coefficient of every order m.
+template <int P, typename T, typename F, typename E>
+__device__ __forceinline__ void basis_values_bands(T x, T y, T z, F&& f, E&& band_end) {
+  const T r2 = x * x + y * y + z * z;
+  T sc = T(1), ss = T(0);
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (m == 1) {
+      sc = x * T(0.5);
+      ss = -y * T(0.5);
+    } else if (m >= 2) {
+      const T fm = T(1.0 / (2 * m));
+      const T nc = (x * sc + y * ss) * fm;
+      const T ns = (x * ss - y * sc) * fm;
+      sc = nc;
+      ss = ns;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    f(m, cidx(m, m), sc);
+    if (m > 0) f(m, cidx(m, -m), ss);
+    T c2 = T(0), s2 = T(0), c1 = sc, s1 = ss;
+#pragma unroll
+    for (int n = m + 1; n <= P; ++n) {
+      T c, s;
+      if (n == m + 1) {
+        c = z * c1;
+        s = z * s1;
+      } else {
+        const T inv = T(1.0 / ((n - m) * (n + m)));
+        const T a = T(2 * n - 1);
+        c = (a * z * c1 - r2 * c2) * inv;
+        s = (a * z * s1 - r2 * s2) * inv;
+      }
+      f(n, cidx(n, m), c);
+      if (m > 0) f(n, cidx(n, -m), s);
+      c2 = c1;
+      s2 = s1;
+      c1 = c;
+      s1 = s;
+    }
+    band_end();
+  }
+}
+
+// Gradient expansions of a local expansion: with u = sum_k w[k] R-hat_k,
+// grad u = sum over degrees <= P-1 of (gx[k], gy[k], gz[k]) R-hat_k.  The
+// regular basis of these recursions satisfies d/dz R_n^m = R_{n-1}^m and
+// (d/dx + i d/dy) R_n^m = R_{n-1}^{m-1}, (d/dx - i d/dy) R_n^m = -R_{n-1}^{m+1}
+// (R_n^m = cos part + i sin part for m >= 0, App. A.1), so every gradient
+// coefficient of degree d and order m' is one or two coefficients of degree
+// d + 1, orders m' +- 1, times +-1/2 (or +-1 next to order 0).  Entry k of
+// g (k < P^2) for k = 0 .. P^2 - 1: gx, gy, gz.
+template <int P, typename T>
+__device__ __forceinline__ void grad_coeff(const T* __restrict__ w, int k, T& gx, T& gy, T& gz) {
+  int d = 0;
+  while ((d + 1) * (d + 1) <= k) ++d;
+  const int m = k - d * d - d;  // signed order, |m| <= d
+  const int am = m < 0 ? -m : m;
+  const int n = d + 1;
+  const T h = T(0.5);
+  gz = w[cidx(n, m)];
+  if (m >= 0) {  // cos part of order am
+    const T up = w[cidx(n, am + 1)], ups = w[cidx(n, -(am + 1))];
+    if (am == 0) {
+      gx = h * up;
+      gy = -(h * ups);
+    } else if (am == 1) {
+      gx = h * up - w[cidx(n, 0)];
+      gy = -(h * ups);
+    } else {
+      gx = h * up - h * w[cidx(n, am - 1)];
+      gy = -(h * ups) - h * w[cidx(n, -(am - 1))];
+    }
+  } else {  // sin part of order am >= 1
+    const T up = w[cidx(n, am + 1)], ups = w[cidx(n, -(am + 1))];
+    if (am == 1) {
+      gx = h * ups;
+      gy = h * up + w[cidx(n, 0)];
+    } else {
+      gx = h * ups - h * w[cidx(n, -(am - 1))];
+      gy = h * up + h * w[cidx(n, am - 1)];
+    }
+  }
+}
+
+// pot = sum_k w[k] R-hat_k and grad = sum_k g[.][k] R-hat_k (g from
+// grad_coeff, degrees <= P-1) over one value sweep of the basis.  In FP32
+// the terms of each order m are summed on their own and the order sums are
 // added with Neumaier compensation.
 template <int P, typename T>
-__device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ w,
-                                           T& pot, T& gx, T& gy, T& gz) {
+__device__ __forceinline__ void local_eval_grad(T x, T y, T z, const T* __restrict__ w,
+                                                const T* __restrict__ gxw,
+                                                const T* __restrict__ gyw,
+                                                const T* __restrict__ gzw, T& pot, T& gx,
+                                                T& gy, T& gz) {
   constexpr bool kComp = sizeof(T) == 4;
   T bp = T(0), bx = T(0), by = T(0), bz = T(0);
   T cp = T(0), cx = T(0), cy = T(0), cz = T(0);
@@ -482,14 +573,15 @@ __device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ 
   T& ax = kComp ? bx : gx;
   T& ay = kComp ? by : gy;
   T& az = kComp ? bz : gz;
-  basis_with_gradient<P, T>(
+  basis_values_bands<P, T>(
       x, y, z,
-      [&](int k, T v, T dx, T dy, T dz) {
-        const T wk = w[k];
-        ap = fma(wk, v, ap);
-        ax = fma(wk, dx, ax);
-        ay = fma(wk, dy, ay);
-        az = fma(wk, dz, az);
+      [&](int n, int k, T v) {
+        ap = fma(w[k], v, ap);
+        if (n < P) {
+          ax = fma(gxw[k], v, ax);
+          ay = fma(gyw[k], v, ay);
+          az = fma(gzw[k], v, az);
+        }
       },
       [&] {
         if (kComp) {
@@ -507,6 +599,7 @@ __device__ __forceinline__ void local_eval(T x, T y, T z, const T* __restrict__ 
     gz += cz;
   }
 }
+
 
 // ---------------------------------------------------------------- P2P
 __device__ __forceinline__ double inv_sqrt(double r2) {

@@ -778,13 +778,14 @@ fmm_status fmm_graph_create(fmm_plan* pl, int transposed, const void* q, int nrh
     g->device = pl->device;
     hipStream_t cs = nullptr;
     FMM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    // the graph holds the stages in one sequence: a second branch for the
-    // near field made replays slower than eager launches (measured on the
-    // 16-problem uneven set: 7.2 against 5.0 ms)
+    // a plan of several problems is captured in one sequence: a second
+    // branch for the near field made its replays slower than eager launches
+    // (16-problem uneven set: 7.2 against 5.0 ms); a plan of one problem
+    // keeps its own choice of stream for the near field
     const bool prof = pl->profiling;
     const int ns = pl->near_stream;
     pl->profiling = false;
-    pl->near_stream = 1;
+    if (pl->n_problems > 1) pl->near_stream = 1;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {

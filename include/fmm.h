@@ -392,9 +392,9 @@ fmm_status fmm_plan_autotune(fmm_plan* plan, const void* q, void* stream, int* p
  *                    of the plan beside the far-field chain (M2M, M2L,
  *                    L2L), forked after P2M and joined before L2P; 1: every
  *                    stage on the caller's stream.  Identical results.
- *                    While stage profiling is on, and inside graphs of a
- *                    plan of several problems (fmm_graph_create), stages
- *                    run one after another on one stream.
+ *                    While stage profiling is on, stages run one after
+ *                    another on one stream; graphs (fmm_graph_create)
+ *                    keep the plan's choice.
  * fmm_plan_set_tiles takes 0 in a field as "the default for this plan" and
  * rejects any other value the plan cannot use (FMM_EINVAL, plan unchanged).
  * fmm_plan_get_tiles writes the values evaluations use (host *tiles).
@@ -423,11 +423,9 @@ fmm_status fmm_plan_destroy(fmm_plan* plan);
  *          addresses: each replay reads q's current contents and rewrites
  *          pot (and field).
  *   out    host, receives the graph (free with fmm_graph_destroy).
- * Nothing runs at creation.  The graph contains kernel launches only; for
- * a plan of one problem whose near field runs on the second stream
- * (near_stream 2) the near field is a second branch of the graph, forked
- * after P2M and joined before L2P; a plan of several problems is captured
- * in one sequence.
+ * Nothing runs at creation.  The graph contains kernel launches only; when
+ * the plan's near field runs on the second stream (near_stream 2) it is a
+ * second branch of the graph, forked after P2M and joined before L2P.
  * Errors: as fmm_evaluate, FMM_EDEVICE if capture or instantiation fails. */
 typedef struct fmm_graph fmm_graph;
 fmm_status fmm_graph_create(fmm_plan* plan, int transposed, const void* q, int nrhs,

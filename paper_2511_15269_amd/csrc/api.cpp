@@ -778,14 +778,11 @@ fmm_status fmm_graph_create(fmm_plan* pl, int transposed, const void* q, int nrh
     g->device = pl->device;
     hipStream_t cs = nullptr;
     FMM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    // a plan of several problems is captured in one sequence: a second
-    // branch for the near field made its replays slower than eager launches
-    // (16-problem uneven set: 7.2 against 5.0 ms); a plan of one problem
-    // keeps its own choice of stream for the near field
+    // the graph keeps the plan's choice of stream for the near field: on
+    // the second stream it becomes a second branch of the graph, forked
+    // after P2M and joined before L2P, as in eager launches
     const bool prof = pl->profiling;
-    const int ns = pl->near_stream;
     pl->profiling = false;
-    if (pl->n_problems > 1) pl->near_stream = 1;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -796,13 +793,11 @@ fmm_status fmm_graph_create(fmm_plan* pl, int transposed, const void* q, int nrh
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipStreamDestroy(cs);
         pl->profiling = prof;
-        pl->near_stream = ns;
         throw;
       }
       e = hipStreamEndCapture(cs, &graph);
     }
     pl->profiling = prof;
-    pl->near_stream = ns;
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
